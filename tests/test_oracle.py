@@ -1,0 +1,327 @@
+"""Pins of the FP64 oracle against facts fixed outside it: published Philox
+known answers, closed forms, special cases, exact brute force on small
+circuits (two independent methods) and deterministic consequences of the
+shared (seed, shot, op) draws. CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dm
+import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def setup_module(_):
+    oracle.build(force=False)
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10
+# --------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "philox_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for row in rows:
+        v = [int(x, 16) for x in row]
+        assert oracle.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_uniform_is_53bit_from_first_two_words():
+    x = oracle.philox4x32_10([5, 0, 7, 0], [3, 0])
+    u = oracle.uniform(3, 5, 7, 0)
+    assert u == ((x[0] >> 5) * 2 ** 26 + (x[1] >> 6)) / 2.0 ** 53
+    hi = oracle.philox4x32_10([0, 1, 2, 9], [0xFFFFFFFF, 0x1])
+    assert oracle.uniform((1 << 32) | 0xFFFFFFFF, 1 << 32, 2, 9) == \
+        ((hi[0] >> 5) * 2 ** 26 + (hi[1] >> 6)) / 2.0 ** 53
+
+
+def test_uniform_statistics():
+    us = np.array([oracle.uniform(11, s, 3, 0) for s in range(20000)])
+    assert us.min() >= 0.0 and us.max() < 1.0
+    assert abs(us.mean() - 0.5) < 4 * math.sqrt(1 / 12 / len(us))
+    assert abs(us.var() - 1 / 12) < 0.005
+    # different d / r fields give uncorrelated streams
+    vs = np.array([oracle.uniform(11, s, 3, 1) for s in range(20000)])
+    assert abs(np.corrcoef(us, vs)[0, 1]) < 0.03
+
+
+# --------------------------------------------------------------------------
+# Gates: special cases, inverse round trip, agreement with an independent
+# dense-matrix application
+# --------------------------------------------------------------------------
+
+def _state(circ, noise=None, shot=0, seed=0, stop_at=-1):
+    _, psi = oracle.run(circ, noise, [shot], seed=seed, stop_at=stop_at,
+                        want_state=True)
+    return psi
+
+
+def test_u3_special_cases():
+    x = {"n_qubits": 1, "n_clbits": 0,
+         "ops": [{"kind": "u3", "qubits": [0], "params": [math.pi, 0, math.pi]}]}
+    psi = _state(x)
+    assert abs(psi[0]) < 1e-15 and abs(psi[1] - 1) < 1e-15
+    h = {"n_qubits": 1, "n_clbits": 0,
+         "ops": [{"kind": "u3", "qubits": [0], "params": [math.pi / 2, 0, math.pi]}]}
+    psi = _state(h)
+    assert np.allclose(psi, [1 / math.sqrt(2), 1 / math.sqrt(2)], atol=1e-15)
+    # U3(0, 0, lambda) is the phase gate diag(1, e^{i lambda}) on |+>
+    p = {"n_qubits": 1, "n_clbits": 0,
+         "ops": [{"kind": "h", "qubits": [0]},
+                 {"kind": "u3", "qubits": [0], "params": [0, 0, 0.3]}]}
+    psi = _state(p)
+    assert np.allclose(psi, np.array([1, np.exp(0.3j)]) / math.sqrt(2), atol=1e-15)
+
+
+def test_round_trip_returns_to_zero_state():
+    circ = W.random_small(5, 60, seed=3, kinds=["u3", "h", "s", "t", "cx", "cz",
+                                                 "swap"], measure_all=False)
+    inv = []
+    for op in reversed(circ["ops"]):
+        k = op["kind"]
+        if k == "u3":
+            th, ph, la = op["params"]
+            inv.append({"kind": "u3", "qubits": op["qubits"], "params": [-th, -la, -ph]})
+        elif k in ("s", "t"):
+            inv.append({"kind": k + "dg", "qubits": op["qubits"]})
+        else:
+            inv.append(op)
+    full = dict(circ, ops=circ["ops"] + inv)
+    psi = _state(full)
+    assert abs(psi[0] - 1) < 1e-13
+    assert np.max(np.abs(psi[1:])) < 1e-13
+
+
+def test_gates_match_independent_dense_application():
+    for seed in range(6):
+        circ = W.random_small(4, 40, seed=seed, measure_all=False)
+        psi = _state(circ)
+        ref = np.zeros(16, dtype=complex)
+        ref[0] = 1
+        for op in circ["ops"]:
+            ref = dm.embed(dm.gate_matrix(op), op["qubits"], 4) @ ref
+        assert np.max(np.abs(psi - ref)) < 1e-13
+        assert abs(np.vdot(psi, psi).real - 1) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Deterministic consequences of the shared draws
+# --------------------------------------------------------------------------
+
+def test_bell_outcome_follows_draw():
+    circ = {"n_qubits": 2, "n_clbits": 2,
+            "ops": [{"kind": "h", "qubits": [0]}, {"kind": "cx", "qubits": [0, 1]},
+                    {"kind": "measure", "qubits": [0, 1], "clbits": [0, 1]}]}
+    mem = oracle.run(circ, None, 4000, seed=9)
+    assert set(np.unique(mem)) <= {0, 3}
+    for s in range(4000):
+        u = oracle.uniform(9, s, 2, 0)
+        assert mem[s] == (0 if u < 0.5 else 3)
+
+
+def test_ghz_counts():
+    n = 5
+    ops = [{"kind": "h", "qubits": [0]}] + \
+        [{"kind": "cx", "qubits": [i, i + 1]} for i in range(n - 1)] + \
+        [{"kind": "measure", "qubits": list(range(n)), "clbits": list(range(n))}]
+    circ = {"n_qubits": n, "n_clbits": n, "ops": ops}
+    mem = oracle.run(circ, None, 3000, seed=1)
+    zeros = sum(1 for s in range(3000) if oracle.uniform(1, s, n, 0) < 0.5)
+    assert int(np.sum(mem == 0)) == zeros
+    assert int(np.sum(mem == 2 ** n - 1)) == 3000 - zeros
+
+
+def test_table1_bitflip_follows_cumulative_threshold():
+    # Table I: 1% bit flip, ID below 0.99, X from 0.99 to 1.00
+    noise = W.noise_model([W.rule(["id"], W.pauli_table([0.99, 0.01], ["I", "X"]))])
+    circ = {"n_qubits": 1, "n_clbits": 1,
+            "ops": [{"kind": "id", "qubits": [0]},
+                    {"kind": "measure", "qubits": [0], "clbits": [0]}]}
+    mem = oracle.run(circ, noise, 20000, seed=4)
+    for s in range(20000):
+        assert mem[s] == (1 if oracle.uniform(4, s, 1, 0) >= 0.99 else 0)
+    assert abs(mem.mean() - 0.01) < 4 * math.sqrt(0.01 * 0.99 / 20000)
+
+
+def test_kraus_choice_follows_running_sum():
+    g = 0.3
+    noise = W.noise_model([W.rule(["h"], W.amplitude_damping_kraus(g))])
+    circ = {"n_qubits": 1, "n_clbits": 1,
+            "ops": [{"kind": "h", "qubits": [0]},
+                    {"kind": "measure", "qubits": [0], "clbits": [0]}]}
+    mem = oracle.run(circ, noise, 5000, seed=2)
+    for s in range(5000):
+        uk = oracle.uniform(2, s, 1, 0)
+        um = oracle.uniform(2, s, 2, 0)
+        if uk >= 1 - g / 2:          # K1 taken: |+> decays to |0>
+            exp = 0
+        else:                        # K0: (|0> + sqrt(1-g)|1>) / sqrt(2-g)
+            exp = 0 if um < 1 / (2 - g) else 1
+        assert mem[s] == exp, s
+
+
+def test_readout_flip_draw():
+    circ = {"n_qubits": 1, "n_clbits": 1,
+            "ops": [{"kind": "measure", "qubits": [0], "clbits": [0]}]}
+    noise = W.noise_model([], readout=(0.1, 0.0))
+    mem = oracle.run(circ, noise, 5000, seed=8)
+    for s in range(5000):
+        assert mem[s] == (1 if oracle.uniform(8, s, 0, 1) < 0.1 else 0)
+
+
+def test_reset_then_measure_is_zero():
+    circ = {"n_qubits": 2, "n_clbits": 4,
+            "ops": [{"kind": "h", "qubits": [0]}, {"kind": "cx", "qubits": [0, 1]},
+                    {"kind": "measure_reset", "qubits": [0, 1], "clbits": [0, 1]},
+                    {"kind": "measure", "qubits": [0, 1], "clbits": [2, 3]}]}
+    mem = oracle.run(circ, None, 2000, seed=5)
+    assert np.all((mem >> 2) == 0)
+    assert set(np.unique(mem & 3)) == {0, 3}
+    circ2 = {"n_qubits": 1, "n_clbits": 1,
+             "ops": [{"kind": "h", "qubits": [0]}, {"kind": "reset", "qubits": [0]},
+                     {"kind": "measure", "qubits": [0], "clbits": [0]}]}
+    assert np.all(oracle.run(circ2, None, 500, seed=5) == 0)
+
+
+def test_state_stays_normalised_through_kraus_and_measure():
+    noise = W.noise_model([W.rule(["u3"], W.amplitude_damping_kraus(0.2)),
+                           W.rule(["cx"], W.depolarizing_pauli(0.3, 2))])
+    circ = W.random_layered(4, 6, seed=2, measure_all=False,
+                            mid_measure=(2, (0, 3)))
+    for shot in range(20):
+        psi = _state(circ, noise, shot=shot)
+        assert abs(np.vdot(psi, psi).real - 1) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Closed forms, exact brute force (density matrix == trajectory tree) and
+# sampled oracle counts against them
+# --------------------------------------------------------------------------
+
+def _sample_check(mem, dist, n_shots, sig=5.0):
+    for key, p in dist.items():
+        c = int(np.sum(mem == key))
+        sd = math.sqrt(max(p * (1 - p), 1e-12) * n_shots)
+        assert abs(c - p * n_shots) <= sig * sd + 1, (key, c, p * n_shots)
+    keys = set(int(k) for k in np.unique(mem))
+    assert keys <= set(k for k, p in dist.items() if p > 0)
+
+
+def test_depolarizing_closed_form():
+    p, k = 0.05, 7
+    noise = W.noise_model([W.rule(["id"], W.depolarizing_pauli(p, 1))])
+    circ = {"n_qubits": 1, "n_clbits": 1,
+            "ops": [{"kind": "id", "qubits": [0]}] * k +
+                   [{"kind": "measure", "qubits": [0], "clbits": [0]}]}
+    exact = (1 - (1 - p) ** k) / 2
+    d = dm.creg_distribution_dm(circ, noise)
+    assert abs(d[1] - exact) < 1e-13
+    t = dm.creg_distribution_tree(circ, noise)
+    assert abs(t[1] - exact) < 1e-13
+    mem = oracle.run(circ, noise, 40000, seed=3)
+    _sample_check(mem, d, 40000)
+
+
+def test_two_qubit_depolarizing_zz_closed_form():
+    p, k = 0.04, 5
+    noise = W.noise_model([W.rule(["id"], W.depolarizing_pauli(p, 2))])
+    # Bell pair, then k identity "gates" on both qubits carrying depol2 noise
+    # (a two-qubit 'id' is expressed as a swap applied twice)
+    ops = [{"kind": "h", "qubits": [0]}, {"kind": "cx", "qubits": [0, 1]}]
+    noise2 = W.noise_model([W.rule(["swap"], W.depolarizing_pauli(p, 2))])
+    ops += [{"kind": "swap", "qubits": [0, 1]}] * (2 * k)
+    ops += [{"kind": "measure", "qubits": [0, 1], "clbits": [0, 1]}]
+    circ = {"n_qubits": 2, "n_clbits": 2, "ops": ops}
+    d = dm.creg_distribution_dm(circ, noise2)
+    zz = d.get(0, 0) + d.get(3, 0) - d.get(1, 0) - d.get(2, 0)
+    assert abs(zz - (1 - p) ** (2 * k)) < 1e-12
+    # the tree has 16 branches per noise site: check it on two sites
+    short = dict(circ, ops=ops[:4] + ops[-1:])
+    t = dm.creg_distribution_tree(short, noise2)
+    ds = dm.creg_distribution_dm(short, noise2)
+    zzt = t.get(0, 0) + t.get(3, 0) - t.get(1, 0) - t.get(2, 0)
+    assert abs(zzt - (1 - p) ** 2) < 1e-12
+    assert dm.tvd(ds, t) < 1e-12
+    mem = oracle.run(circ, noise2, 40000, seed=6)
+    _sample_check(mem, d, 40000)
+
+
+def test_amplitude_damping_closed_form():
+    g, k = 0.1, 6
+    noise = W.noise_model([W.rule(["id"], W.amplitude_damping_kraus(g))])
+    for prep, factor in (("x", 1.0), ("h", 0.5)):
+        circ = {"n_qubits": 1, "n_clbits": 1,
+                "ops": [{"kind": prep, "qubits": [0]}] +
+                       [{"kind": "id", "qubits": [0]}] * k +
+                       [{"kind": "measure", "qubits": [0], "clbits": [0]}]}
+        d = dm.creg_distribution_dm(circ, noise)
+        assert abs(d[1] - factor * (1 - g) ** k) < 1e-13
+        t = dm.creg_distribution_tree(circ, noise)
+        assert abs(t[1] - factor * (1 - g) ** k) < 1e-13
+        mem = oracle.run(circ, noise, 40000, seed=12)
+        _sample_check(mem, d, 40000)
+
+
+def test_readout_closed_form():
+    circ = {"n_qubits": 1, "n_clbits": 1,
+            "ops": [{"kind": "x", "qubits": [0]},
+                    {"kind": "measure", "qubits": [0], "clbits": [0]}]}
+    noise = W.noise_model([], readout=(0.0, 0.07))
+    d = dm.creg_distribution_dm(circ, noise)
+    assert abs(d[0] - 0.07) < 1e-15
+    mem = oracle.run(circ, noise, 20000, seed=1)
+    _sample_check(mem, d, 20000)
+
+
+def _random_noise(seed):
+    rng = np.random.default_rng(seed)
+    # a random CPTP single-qubit Kraus channel from a random isometry
+    z = rng.normal(size=(6, 2)) + 1j * rng.normal(size=(6, 2))
+    v, _ = np.linalg.qr(z)
+    mats = [v[2 * i:2 * i + 2, :] for i in range(3)]
+    return W.noise_model(
+        [W.rule(["u3", "h"], W.depolarizing_pauli(0.2, 1)),
+         W.rule(["u3"], W.amplitude_damping_kraus(0.25)),
+         W.rule(["t", "s"], W.kraus_channel(mats)),
+         W.rule(["cx", "cz"], W.depolarizing_pauli(0.15, 2))],
+        readout=(0.03, 0.06))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_dm_equals_tree_and_oracle_samples(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = 2 + seed % 2
+    circ = W.random_small(n, 4, seed=seed, kinds=["u3", "h", "t", "s", "cx", "cz"],
+                          n_mid=1)
+    noise = _random_noise(seed)
+    d = dm.creg_distribution_dm(circ, noise)
+    t = dm.creg_distribution_tree(circ, noise)
+    assert abs(sum(d.values()) - 1) < 1e-12
+    assert dm.tvd(d, t) < 1e-12
+    shots = 30000
+    mem = oracle.run(circ, noise, shots, seed=int(rng.integers(1 << 30)))
+    _sample_check(mem, d, shots)
+
+
+def test_oracle_sample_mismatch_detects_wrong_channel_order():
+    # Depolarizing-then-damping and damping-then-depolarizing are different
+    # channels; the sampled check must tell them apart (guards the rule
+    # order of the noise expansion).
+    circ = {"n_qubits": 1, "n_clbits": 1,
+            "ops": [{"kind": "x", "qubits": [0]}, {"kind": "id", "qubits": [0]},
+                    {"kind": "measure", "qubits": [0], "clbits": [0]}]}
+    a = W.noise_model([W.rule(["x", "id"], W.pauli_table([0.5, 0.5], ["I", "X"])),
+                       W.rule(["x", "id"], W.amplitude_damping_kraus(0.9))])
+    b = W.noise_model([W.rule(["x", "id"], W.amplitude_damping_kraus(0.9)),
+                       W.rule(["x", "id"], W.pauli_table([0.5, 0.5], ["I", "X"]))])
+    da = dm.creg_distribution_dm(circ, a)
+    db = dm.creg_distribution_dm(circ, b)
+    assert dm.tvd(da, db) > 0.1
+    mem = oracle.run(circ, a, 20000, seed=0)
+    _sample_check(mem, da, 20000)
