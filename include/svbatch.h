@@ -1,0 +1,210 @@
+/*
+ * svbatch.h -- C ABI of the MI355X multi-shot noisy state-vector library.
+ *
+ * The library runs many shots of one noisy quantum circuit on one gfx950 GPU
+ * and returns the bit-count histogram of the classical register, the problem
+ * statement of Doi, Horii and Wood, "Efficient techniques to GPU
+ * Accelerations of Multi-Shot Quantum Computing Simulations" (arXiv
+ * 2308.03399), Sec. III-B: a circuit, a noise model and a shot count go in,
+ * a bit-count array comes out. Inside one launch it applies the circuit's
+ * gates to per-shot 2^n-amplitude state vectors, samples per-shot Pauli
+ * noise (Sec. IV-A, Pauli batching), selects per-shot Kraus operators
+ * (Sec. IV-A, Kraus batching), performs mid-circuit measure/reset
+ * (Sec. IV-A, measure/reset) and, in branch mode, shares one state among
+ * shots until a draw splits them (Sec. IV-B, shot-branching).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns sv_status; no C++ exception crosses the ABI.
+ *    On failure, sv_last_error() returns a thread-local message.
+ *  - Host pointers are borrowed for the duration of the call only; the
+ *    library copies what it keeps. Device memory is NOT allocated by the
+ *    library: the caller attaches one device arena (sv_batch_attach) whose
+ *    size is given by sv_batch_footprint, and a HIP stream on which all work
+ *    is enqueued.
+ *  - Calls on one handle must be serialised by the caller. Different
+ *    handles may be used from different threads.
+ *  - Basis index bit q is the value of qubit q (little-endian). Amplitudes
+ *    of a state are stored contiguously, shot after shot (Sec. IV-A, data
+ *    structure).
+ *  - Random numbers: every random decision of shot s at expanded-op index r
+ *    uses U(seed, s, r, d) of Philox4x32-10 (key = seed, counter =
+ *    (s lo, s hi, r, d)), so the result of a shot does not depend on the
+ *    mode, batch size, branching or number of relaunches.
+ */
+#ifndef SVBATCH_H
+#define SVBATCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sv_batch sv_batch; /* opaque; freed by sv_batch_destroy */
+
+typedef enum { SV_C64 = 0, SV_C128 = 1 } sv_dtype;
+
+typedef enum {
+    SV_OK = 0,
+    SV_EINVAL = 1,        /* invalid argument, circuit or noise model     */
+    SV_ENOMEM = 2,        /* arena too small (not even one state fits)    */
+    SV_EDEVICE = 3,       /* HIP error, or a device-side failure flag     */
+    SV_ESTATE = 4,        /* call out of order (e.g. run before attach)   */
+    SV_EUNSUPPORTED = 5   /* valid request outside what is implemented    */
+} sv_status;
+
+typedef enum {
+    SV_MODE_BATCH = 0,    /* every shot owns a state (Sec. IV-A)          */
+    SV_MODE_BRANCH = 1,   /* shots share states until split (Sec. IV-B)   */
+    SV_MODE_PLAIN = 2     /* one state, one kernel per op, host decisions */
+} sv_mode;
+
+/* Op kinds of sv_op.kind. Gates act on q[0..nq-1]; for CX q[0] is the
+ * control; for SV_OP_UNITARY bit t of the matrix row/column index is the
+ * value of qubit q[t]. */
+typedef enum {
+    SV_OP_ID = 1, SV_OP_X, SV_OP_Y, SV_OP_Z, SV_OP_H, SV_OP_S, SV_OP_SDG,
+    SV_OP_T, SV_OP_TDG,
+    SV_OP_U3 = 10,        /* p = {theta, phi, lambda}, OpenQASM 2 U3        */
+    SV_OP_CX = 20, SV_OP_CZ, SV_OP_SWAP,
+    SV_OP_UNITARY = 30,   /* 1 or 2 qubits, dense matrix in mat            */
+    SV_OP_MEASURE = 40,   /* qubits -> clbits (Sec. IV-A measure)           */
+    SV_OP_RESET,          /* measure without record, then back to |0>      */
+    SV_OP_MEASURE_RESET   /* measure -> clbits, then back to |0>           */
+} sv_op_kind;
+
+#define SV_MAX_INLINE 8   /* qubits/clbits held inline in sv_op            */
+#define SV_MAX_CLBITS 64
+
+typedef struct {
+    uint32_t kind;                  /* sv_op_kind                                  */
+    uint32_t nq;                    /* number of qubits (and clbits for measures)  */
+    uint32_t q[SV_MAX_INLINE];      /* qubits, used when nq <= SV_MAX_INLINE       */
+    uint32_t c[SV_MAX_INLINE];      /* clbits of MEASURE / MEASURE_RESET           */
+    double p[3];                    /* SV_OP_U3 angles                             */
+    const double *mat;              /* SV_OP_UNITARY: (2^nq)^2 complex, row-major,
+                                       interleaved re/im; copied during the call   */
+    const uint32_t *q_ext;          /* qubits when nq > SV_MAX_INLINE, else NULL   */
+    const uint32_t *c_ext;          /* clbits when nq > SV_MAX_INLINE, else NULL   */
+} sv_op;
+
+/* Pauli channel (Sec. III-B, Table I): n_terms (probability, Pauli string)
+ * entries. pauli[j*nq + t] is the code of term j on the gate's qubit t,
+ * I=0 X=1 Y=2 Z=3. Probabilities must be >= 0 and sum to 1 within 1e-12;
+ * the entry taken is the first whose running sum exceeds the draw. */
+typedef struct {
+    uint32_t nq, n_terms;
+    const double *prob;
+    const uint8_t *pauli;
+} sv_pauli_channel;
+
+/* Kraus channel (Sec. III-B, Kraus operator): n_mats matrices of
+ * (2^nq)^2 complex entries, row-major, interleaved re/im, with
+ * sum_j K_j^dagger K_j = I within 1e-10. nq is 1 or 2. */
+typedef struct {
+    uint32_t nq, n_mats;
+    const double *mats;
+} sv_kraus_channel;
+
+/* A noise rule is attached after every gate whose kind bit is set in
+ * gate_kinds_mask (bit k <-> sv_op_kind k) and whose qubit count equals the
+ * channel's nq, on the gate's qubits, in rule order (the all-qubit error
+ * rules of the paper's noise-model example, Sec. III-B). */
+typedef struct {
+    uint64_t gate_kinds_mask;
+    uint32_t is_kraus;              /* 0: channel is sv_pauli_channel*, 1: sv_kraus_channel* */
+    const void *channel;
+} sv_noise_rule;
+
+/* Readout error (named in Sec. III-B): each recorded bit flips 0->1 with
+ * readout_p01 and 1->0 with readout_p10, from its own draw d = 1 + t. */
+typedef struct {
+    uint32_t n_rules;
+    const sv_noise_rule *rules;
+    double readout_p01, readout_p10;
+} sv_noise_model;
+
+typedef struct {
+    double kernel_ms;          /* device time of the last run (HIP events)         */
+    uint64_t passes;           /* state passes executed (tile sweeps of a state)   */
+    uint64_t amp_bytes;        /* algorithmic bytes: passes * 2 * 2^n * amp size
+                                  plus read-only reduction sweeps and copies       */
+    uint64_t reductions;       /* FP64 reductions deciding Kraus/measure ops       */
+    uint64_t branches;         /* states created by splits (branch mode)           */
+    uint64_t restarts;         /* waiting-list relaunches (branch mode)            */
+    uint64_t waiting_shots;    /* shots parked on the waiting list, summed         */
+    uint64_t expanded_ops;     /* ops after noise-site expansion                   */
+    uint64_t gate_count;       /* original gates (metric numerator per shot)       */
+    uint32_t workers;          /* persistent workgroups launched                   */
+    uint32_t slots;            /* state slots in the arena                         */
+    uint32_t tile_qubits;      /* qubits per LDS tile                              */
+    uint32_t static_passes;    /* passes of the static plan                        */
+    uint64_t flops;            /* algorithmic flops of the applied ops             */
+} sv_stats;
+
+/* Create a handle for n_qubits (1..30) and n_shots (>= 1) in the given
+ * storage dtype. No device work. SV_EINVAL on bad sizes. */
+sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
+                          sv_batch **out);
+
+/* Options (call before sv_batch_attach; some also between runs):
+ *   "mode"         sv_mode                                   (default BATCH)
+ *   "slots"        state slots in the arena; 0 = automatic
+ *   "workers"      persistent workgroups; 0 = automatic (fills the GPU)
+ *   "tile_qubits"  qubits per LDS tile, 6..14; 0 = automatic
+ *   "program_bytes" device bytes reserved for the op program (default 8 MiB)
+ *   "dump_shot"    shot id whose state before the final op is kept for
+ *                  sv_get_state; -1 disables (default)
+ *   "spin_limit_ms" device wait bound of the work queue (default 300000)
+ * SV_EINVAL on an unknown key or bad value, SV_ESTATE if already attached
+ * for keys that change the footprint. */
+sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t value);
+
+/* Device bytes the arena must hold for the current options, and the bytes
+ * of one state (2^n * 8 for C64, 2^n * 16 for C128). Needs a visible GPU to
+ * size the worker count. */
+sv_status sv_batch_footprint(const sv_batch *b, uint64_t *bytes_required,
+                             uint64_t *bytes_per_state);
+
+/* Attach a caller-owned device buffer (at least sv_batch_footprint bytes,
+ * 256-byte aligned) and the hipStream_t all work is enqueued on (NULL: the
+ * null stream). The arena stays owned by the caller and must outlive the
+ * handle's use. SV_ENOMEM if too small. */
+sv_status sv_batch_attach(sv_batch *b, void *device_arena, uint64_t arena_bytes,
+                          void *hip_stream);
+
+/* Run all shots of the circuit ops[0..n_ops-1] under the noise model nm
+ * (NULL: noiseless) with Philox seed `seed`. Validates first (qubits < n and
+ * distinct within an op, clbits < 64, probabilities, Kraus completeness):
+ * SV_EINVAL without touching the device. Blocks until the device work of
+ * the run has finished. On any failure the handle is left in a state where
+ * results are unavailable until the next successful run. */
+sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops,
+                         const sv_noise_model *nm, uint64_t seed);
+
+/* Bit-count histogram of the last run (Sec. III-B): keys[i] is a classical
+ * register value (clbit c <-> bit c), counts[i] its number of shots, keys
+ * ascending. If capacity < the number of distinct keys, *n_unique receives
+ * the required size and SV_EINVAL is returned. */
+sv_status sv_sample_counts(sv_batch *b, uint64_t *keys, uint64_t *counts,
+                           size_t capacity, size_t *n_unique);
+
+/* Per-shot classical registers of the last run ("memory"), shot order;
+ * n must equal the shot count. */
+sv_status sv_get_memory(sv_batch *b, uint64_t *creg_per_shot, size_t n);
+
+/* State of shot "dump_shot" before the last op of the circuit (normalised,
+ * interleaved re/im doubles, 2^n complex). SV_ESTATE if none was kept. */
+sv_status sv_get_state(sv_batch *b, double *amps, size_t n_amps);
+
+sv_status sv_get_stats(sv_batch *b, sv_stats *out);
+
+sv_status sv_batch_destroy(sv_batch *b);
+
+const char *sv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVBATCH_H */

@@ -1,0 +1,1551 @@
+// Persistent multi-shot executor for gfx950.
+//
+// One workgroup owns one state at a time and runs the whole expanded op list
+// on it (batch-shots of Sec. IV-A: all shots in one launch; shot-branching of
+// Sec. IV-B: a state shared by a range of shots, split when their draws
+// disagree). Ops are applied in LDS tiles of 2^k amplitudes: a tile holds
+// the k "tile qubits" of the current pass (always including qubits 0..3 so
+// that global accesses are 128-byte runs) and one fixed value of the other
+// qubits. When the whole state fits in LDS (n <= k) it never leaves LDS.
+//
+// Random decisions are taken per shot from Philox4x32-10 draws keyed by
+// (seed, shot, expanded-op index):
+//  * Pauli channels: first table entry whose running sum exceeds u.
+//  * Kraus channels: first K_j whose running sum of ||K_j psi||^2 exceeds
+//    u*||psi||^2 (FP64 reduction over the state). When u is below the
+//    smallest eigenvalue of K_0^dagger K_0 the choice is K_0 whatever the
+//    state is, so no reduction is needed; K_0 is then applied without
+//    renormalisation (every later decision compares against the norm of the
+//    same reduction, so the scale cancels).
+//  * Measure: FP64 outcome probabilities, first running sum above u*N.
+//  * Final measurement of all qubits: chunked FP64 prefix sums (tile sums,
+//    then an in-tile scan) and a search per shot (sampling technique).
+// Reductions use a fixed tree: thread-sequential, wave butterfly, then the
+// four waves in order, then tiles in order, so results do not depend on the
+// batch or the launch shape.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "program.h"
+
+namespace svb {
+
+template <class R> struct V2;
+template <> struct V2<float> { using T = float2; };
+template <> struct V2<double> { using T = double2; };
+
+// ------------------------------------------------------------------ RNG
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies with the published multipliers, the key bumped by
+// the two Weyl constants between rounds.
+__device__ __forceinline__ double philox_u01(uint64_t seed, uint64_t shot,
+                                             uint32_t r, uint32_t d)
+{
+    uint32_t x0 = (uint32_t)shot, x1 = (uint32_t)(shot >> 32), x2 = r, x3 = d;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t a = 0xD2511F53u * x0, ah = __umulhi(0xD2511F53u, x0);
+        const uint32_t b = 0xCD9E8D57u * x2, bh = __umulhi(0xCD9E8D57u, x2);
+        const uint32_t y0 = bh ^ x1 ^ k0, y2 = ah ^ x3 ^ k1;
+        x0 = y0; x1 = b; x2 = y2; x3 = a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    const uint64_t v = ((uint64_t)(x0 >> 5) << 26) | (uint64_t)(x1 >> 6);
+    return (double)v * 0x1.0p-53;
+}
+
+// ------------------------------------------------------------------ misc
+__device__ __forceinline__ uint32_t ins0(uint32_t p, uint32_t b)
+{
+    const uint32_t lo = p & ((1u << b) - 1u);
+    return ((p ^ lo) << 1) | lo;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t ld_rlx(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_rlx_i(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class R> struct Mat2 { R r[4], i[4]; };
+
+template <class R>
+__device__ __forceinline__ Mat2<R> load_m2(const double *m, double s)
+{
+    Mat2<R> o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        o.r[e] = (R)(m[2 * e] * s);
+        o.i[e] = (R)(m[2 * e + 1] * s);
+    }
+    return o;
+}
+
+// acc + (mr + i mi) * v
+template <class A, class R>
+__device__ __forceinline__ A cmac(A acc, R mr, R mi, A v)
+{
+    acc.x = fma(mr, v.x, fma(-mi, v.y, acc.x));
+    acc.y = fma(mr, v.y, fma(mi, v.x, acc.y));
+    return acc;
+}
+
+template <class A, class R>
+__device__ __forceinline__ A cmul(R mr, R mi, A v)
+{
+    A o;
+    o.x = fma(mr, v.x, -mi * v.y);
+    o.y = fma(mr, v.y, mi * v.x);
+    return o;
+}
+
+// Exact multiplication by (-i)^ny.
+template <class A>
+__device__ __forceinline__ A phase_ny(A v, uint32_t ny)
+{
+    A o;
+    switch (ny & 3u) {
+    case 0: o = v; break;
+    case 1: o.x = v.y; o.y = -v.x; break;
+    case 2: o.x = -v.x; o.y = -v.y; break;
+    default: o.x = -v.y; o.y = v.x; break;
+    }
+    return o;
+}
+
+template <class A>
+__device__ __forceinline__ A neg_if(A v, uint32_t odd)
+{
+    if (odd & 1u) { v.x = -v.x; v.y = -v.y; }
+    return v;
+}
+
+template <class A>
+__device__ __forceinline__ double abs2d(A v)
+{
+    const double x = (double)v.x, y = (double)v.y;
+    return fma(x, x, y * y);
+}
+
+// ------------------------------------------------------------------ shared
+enum StopKind { STOP_NONE = 0, STOP_REDUCE = 1, STOP_SPLIT = 2,
+                STOP_TERMINAL = 3, STOP_END = 4 };
+enum Status { ST_WORK = 0, ST_EXIT = 1 };
+
+struct WgShared {
+    BranchRec rec;
+    int status;
+    int slot;        // state slot (streamed mode), -1 if none
+    int fresh;       // slot holds the virtual |0..0> state
+    int lo, hi;      // shot range
+    int cursor;
+    int pending;
+    double first_scale;
+    double norm_lb;
+    int start, end, stop, stop_op;
+    int omin, omax, anyhigh;
+    int n_groups;
+    int grp_o[16];
+    int grp_lo[16];
+    int grp_hi[16];
+    int tot[16];
+    int alloc_slot;
+    int wait_base;
+    int dump_here;
+    double red[kMaxRed];
+    double wred[kMaxRed][kWG / 64];
+    double tsum_n;
+    int term_tile;
+    unsigned long long st[ST_COUNT];
+};
+
+template <class R>
+struct Ctx {
+    using A = typename V2<R>::T;
+    const ExecParams &P;
+    WgShared &S;
+    A *L;              // LDS tile (2^k amplitudes)
+    uint32_t *hi_off;  // LDS: global offset of local index bits >= 4
+    int *dec;          // LDS: decided outcome of each op of the pass
+    int *cnt;          // LDS: 16 x kWG outcome counters (splits)
+    uint32_t tsize;    // 2^k
+    uint32_t n_tiles;  // 2^(n-k), 1 if resident
+    int tid;
+};
+
+// ----------------------------------------------------------- op sweeps
+template <class R>
+__device__ void sweep_mat1(Ctx<R> &c, uint32_t b, const Mat2<R> &m, bool diag)
+{
+    using A = typename V2<R>::T;
+    A *L = c.L;
+    if (diag) {
+        for (uint32_t i = c.tid; i < c.tsize; i += kWG) {
+            const A v = L[i];
+            L[i] = ((i >> b) & 1u) ? cmul<A, R>(m.r[3], m.i[3], v)
+                                   : cmul<A, R>(m.r[0], m.i[0], v);
+        }
+    } else {
+        const uint32_t half = c.tsize >> 1, bit = 1u << b;
+        for (uint32_t p = c.tid; p < half; p += kWG) {
+            const uint32_t i0 = ins0(p, b), i1 = i0 | bit;
+            const A a = L[i0], d = L[i1];
+            A o0 = cmul<A, R>(m.r[0], m.i[0], a);
+            o0 = cmac<A, R>(o0, m.r[1], m.i[1], d);
+            A o1 = cmul<A, R>(m.r[2], m.i[2], a);
+            o1 = cmac<A, R>(o1, m.r[3], m.i[3], d);
+            L[i0] = o0;
+            L[i1] = o1;
+        }
+    }
+    __syncthreads();
+}
+
+// 4x4 matrix, row-major interleaved re/im in doubles, index bit t <-> b[t].
+template <class R>
+__device__ void sweep_mat2(Ctx<R> &c, uint32_t b0, uint32_t b1, const double *m,
+                           double s)
+{
+    using A = typename V2<R>::T;
+    R mr[16], mi[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        mr[e] = (R)(m[2 * e] * s);
+        mi[e] = (R)(m[2 * e + 1] * s);
+    }
+    const uint32_t lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
+    const uint32_t quarter = c.tsize >> 2;
+    const uint32_t m0 = 1u << b0, m1 = 1u << b1;
+    A *L = c.L;
+    for (uint32_t p = c.tid; p < quarter; p += kWG) {
+        const uint32_t base = ins0(ins0(p, lo), hi);
+        const uint32_t idx[4] = {base, base | m0, base | m1, base | m0 | m1};
+        A v[4], o[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) v[a] = L[idx[a]];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            A acc = cmul<A, R>(mr[4 * a], mi[4 * a], v[0]);
+#pragma unroll
+            for (int bb = 1; bb < 4; ++bb)
+                acc = cmac<A, R>(acc, mr[4 * a + bb], mi[4 * a + bb], v[bb]);
+            o[a] = acc;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) L[idx[a]] = o[a];
+    }
+    __syncthreads();
+}
+
+template <class R>
+__device__ void sweep_cx(Ctx<R> &c, uint32_t bc, uint32_t bt)
+{
+    using A = typename V2<R>::T;
+    const uint32_t lo = bc < bt ? bc : bt, hi = bc < bt ? bt : bc;
+    const uint32_t quarter = c.tsize >> 2;
+    A *L = c.L;
+    for (uint32_t p = c.tid; p < quarter; p += kWG) {
+        const uint32_t i = ins0(ins0(p, lo), hi) | (1u << bc);
+        const uint32_t j = i | (1u << bt);
+        const A a = L[i];
+        L[i] = L[j];
+        L[j] = a;
+    }
+    __syncthreads();
+}
+
+template <class R>
+__device__ void sweep_cz(Ctx<R> &c, uint32_t ba, uint32_t bb)
+{
+    using A = typename V2<R>::T;
+    const uint32_t lo = ba < bb ? ba : bb, hi = ba < bb ? bb : ba;
+    const uint32_t quarter = c.tsize >> 2;
+    A *L = c.L;
+    for (uint32_t p = c.tid; p < quarter; p += kWG) {
+        const uint32_t i = ins0(ins0(p, lo), hi) | (1u << ba) | (1u << bb);
+        A a = L[i];
+        a.x = -a.x;
+        a.y = -a.y;
+        L[i] = a;
+    }
+    __syncthreads();
+}
+
+template <class R>
+__device__ void sweep_swap(Ctx<R> &c, uint32_t ba, uint32_t bb)
+{
+    using A = typename V2<R>::T;
+    const uint32_t lo = ba < bb ? ba : bb, hi = ba < bb ? bb : ba;
+    const uint32_t quarter = c.tsize >> 2;
+    A *L = c.L;
+    for (uint32_t p = c.tid; p < quarter; p += kWG) {
+        const uint32_t base = ins0(ins0(p, lo), hi);
+        const uint32_t i = base | (1u << ba), j = base | (1u << bb);
+        const A a = L[i];
+        L[i] = L[j];
+        L[j] = a;
+    }
+    __syncthreads();
+}
+
+// Pauli string P = (-i)^ny Z^z X^x on local masks (Sec. IV-A, Pauli batching:
+// swap of the amplitudes paired by the X/Y mask, phase from the Y count,
+// sign from the parity of the destination index under the Z/Y mask).
+template <class R>
+__device__ void sweep_pauli(Ctx<R> &c, uint32_t xl, uint32_t zl, uint32_t ny)
+{
+    using A = typename V2<R>::T;
+    A *L = c.L;
+    if (xl == 0) {
+        for (uint32_t i = c.tid; i < c.tsize; i += kWG)
+            L[i] = phase_ny(neg_if(L[i], __popc(i & zl)), ny);
+    } else {
+        const uint32_t xb = 31u - __clz(xl);
+        const uint32_t half = c.tsize >> 1;
+        for (uint32_t p = c.tid; p < half; p += kWG) {
+            const uint32_t i0 = ins0(p, xb), i1 = i0 ^ xl;
+            const A a = L[i0], d = L[i1];
+            L[i0] = phase_ny(neg_if(d, __popc(i0 & zl)), ny);
+            L[i1] = phase_ny(neg_if(a, __popc(i1 & zl)), ny);
+        }
+    }
+    __syncthreads();
+}
+
+// Collapse onto outcome pattern o of the measured local bits, scale by s,
+// then (reset) return measured ones to |0>.
+template <class R>
+__device__ void sweep_measure(Ctx<R> &c, const DevOp &op, uint32_t o, double s)
+{
+    using A = typename V2<R>::T;
+    A *L = c.L;
+    const R sc = (R)s;
+    for (uint32_t i = c.tid; i < c.tsize; i += kWG) {
+        uint32_t pat = 0;
+        for (int t = 0; t < op.nq; ++t) pat |= ((i >> op.lb[t]) & 1u) << t;
+        A v = L[i];
+        if (pat == o) {
+            v.x *= sc;
+            v.y *= sc;
+        } else {
+            v.x = 0;
+            v.y = 0;
+        }
+        L[i] = v;
+    }
+    __syncthreads();
+    if (op.flags & DF_RESET) {
+        for (int t = 0; t < op.nq; ++t) {
+            if (!((o >> t) & 1u)) continue;
+            const uint32_t b = op.lb[t], half = c.tsize >> 1;
+            for (uint32_t p = c.tid; p < half; p += kWG) {
+                const uint32_t i0 = ins0(p, b), i1 = i0 | (1u << b);
+                const A a = L[i0];
+                L[i0] = L[i1];
+                L[i1] = a;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t flops_mat1(bool diag) { return diag ? 6 : 14; }
+
+// Apply op j with decided outcome d (and renormalisation s) to the tile.
+template <class R>
+__device__ void apply_op(Ctx<R> &c, const DevOp &op, int d, double s)
+{
+    const ExecParams &P = c.P;
+    switch (op.kind) {
+    case DK_MAT1: {
+        const Mat2<R> m = load_m2<R>(P.pool + op.mat, 1.0);
+        sweep_mat1(c, op.lb[0], m, (op.flags & DF_DIAG) != 0);
+        break;
+    }
+    case DK_MAT2:
+        sweep_mat2(c, op.lb[0], op.lb[1], P.pool + op.mat, 1.0);
+        break;
+    case DK_CX: sweep_cx(c, op.lb[0], op.lb[1]); break;
+    case DK_CZ: sweep_cz(c, op.lb[0], op.lb[1]); break;
+    case DK_SWAP: sweep_swap(c, op.lb[0], op.lb[1]); break;
+    case DK_PAULI: {
+        const DevRule &ru = P.rules[op.rule];
+        if ((ru.ident_mask >> d) & 1u) break;
+        uint32_t xl = 0, zl = 0;
+        for (int t = 0; t < op.nq; ++t) {
+            xl |= ((ru.xcode[d] >> t) & 1u) << op.lb[t];
+            zl |= ((ru.zcode[d] >> t) & 1u) << op.lb[t];
+        }
+        sweep_pauli(c, xl, zl, ru.ny[d]);
+        break;
+    }
+    case DK_KRAUS: {
+        const DevRule &ru = P.rules[op.rule];
+        const uint32_t dim = 1u << ru.nq;
+        const double *m = P.pool + ru.mats + (size_t)d * dim * dim * 2;
+        if (ru.nq == 1) {
+            const Mat2<R> mm = load_m2<R>(m, s);
+            const bool diag = m[2] == 0.0 && m[3] == 0.0 && m[4] == 0.0 && m[5] == 0.0;
+            sweep_mat1(c, op.lb[0], mm, diag);
+        } else {
+            sweep_mat2(c, op.lb[0], op.lb[1], m, s);
+        }
+        break;
+    }
+    case DK_MEASURE:
+        sweep_measure(c, op, (uint32_t)d, s);
+        break;
+    default: break;
+    }
+}
+
+__device__ __forceinline__ uint64_t op_flops(const ExecParams &P, const DevOp &op, int d)
+{
+    switch (op.kind) {
+    case DK_MAT1: return flops_mat1((op.flags & DF_DIAG) != 0);
+    case DK_MAT2: return 30;
+    case DK_KRAUS: return P.rules[op.rule].nq == 1 ? 14 : 30;
+    case DK_MEASURE: return 2;
+    default: return 0;
+    }
+}
+
+// ----------------------------------------------------------- reductions
+// Accumulate, over the tile, the squared norm and the candidate weights of
+// op `op` (Kraus: ||K_j v||^2; measure: outcome probabilities).
+template <class R>
+__device__ void reduce_tile(Ctx<R> &c, const DevOp &op, double (&acc)[kMaxRed])
+{
+    using A = typename V2<R>::T;
+    const ExecParams &P = c.P;
+    A *L = c.L;
+    if (op.kind == DK_KRAUS) {
+        const DevRule &ru = P.rules[op.rule];
+        const int nm = ru.n_terms;
+        const double *K = P.pool + ru.mats;
+        if (ru.nq == 1) {
+            const uint32_t b = op.lb[0], half = c.tsize >> 1;
+            for (uint32_t p = c.tid; p < half; p += kWG) {
+                const uint32_t i0 = ins0(p, b), i1 = i0 | (1u << b);
+                const A a = L[i0], d = L[i1];
+                const double ar = a.x, ai = a.y, dr = d.x, di = d.y;
+                acc[0] += fma(ar, ar, ai * ai) + fma(dr, dr, di * di);
+#pragma unroll
+                for (int j = 0; j < kMaxKraus; ++j) {
+                    if (j >= nm) break;
+                    const double *m = K + j * 8;
+                    const double w0r = m[0] * ar - m[1] * ai + m[2] * dr - m[3] * di;
+                    const double w0i = m[0] * ai + m[1] * ar + m[2] * di + m[3] * dr;
+                    const double w1r = m[4] * ar - m[5] * ai + m[6] * dr - m[7] * di;
+                    const double w1i = m[4] * ai + m[5] * ar + m[6] * di + m[7] * dr;
+                    acc[1 + j] += fma(w0r, w0r, w0i * w0i) + fma(w1r, w1r, w1i * w1i);
+                }
+            }
+        } else {
+            const uint32_t b0 = op.lb[0], b1 = op.lb[1];
+            const uint32_t lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
+            const uint32_t quarter = c.tsize >> 2;
+            for (uint32_t p = c.tid; p < quarter; p += kWG) {
+                const uint32_t base = ins0(ins0(p, lo), hi);
+                const uint32_t idx[4] = {base, base | (1u << b0), base | (1u << b1),
+                                         base | (1u << b0) | (1u << b1)};
+                double vr[4], vi[4];
+                for (int a = 0; a < 4; ++a) {
+                    const A v = L[idx[a]];
+                    vr[a] = v.x;
+                    vi[a] = v.y;
+                    acc[0] += fma(vr[a], vr[a], vi[a] * vi[a]);
+                }
+#pragma unroll
+                for (int j = 0; j < kMaxKraus; ++j) {
+                    if (j >= nm) break;
+                    const double *m = K + j * 32;
+                    double s = 0;
+                    for (int a = 0; a < 4; ++a) {
+                        double wr = 0, wi = 0;
+                        for (int bb = 0; bb < 4; ++bb) {
+                            const double mr = m[2 * (4 * a + bb)], mi = m[2 * (4 * a + bb) + 1];
+                            wr += mr * vr[bb] - mi * vi[bb];
+                            wi += mr * vi[bb] + mi * vr[bb];
+                        }
+                        s += fma(wr, wr, wi * wi);
+                    }
+                    acc[1 + j] += s;
+                }
+            }
+        }
+    } else {  // DK_MEASURE
+        for (uint32_t i = c.tid; i < c.tsize; i += kWG) {
+            uint32_t pat = 0;
+            for (int t = 0; t < op.nq; ++t) pat |= ((i >> op.lb[t]) & 1u) << t;
+            const double w = abs2d(L[i]);
+            acc[0] += w;
+#pragma unroll
+            for (int o = 0; o < 16; ++o) acc[1 + o] += (pat == (uint32_t)o) ? w : 0.0;
+        }
+    }
+}
+
+// Sum acc[0..cnt) over the workgroup into S.red (fixed order).
+template <class R>
+__device__ void wg_reduce(Ctx<R> &c, double (&acc)[kMaxRed], int cnt)
+{
+    const int lane = c.tid & 63, wv = c.tid >> 6;
+#pragma unroll
+    for (int v = 0; v < kMaxRed; ++v) {
+        if (v < cnt) {
+            const double s = wave_sum(acc[v]);
+            if (lane == 0) c.S.wred[v][wv] = s;
+        }
+    }
+    __syncthreads();
+    if (c.tid < cnt) {
+        double s = 0;
+        for (int w = 0; w < kWG / 64; ++w) s += c.S.wred[c.tid][w];
+        c.S.red[c.tid] = s;
+    }
+    __syncthreads();
+}
+
+// Sum of one value over the workgroup; result valid in every thread.
+template <class R>
+__device__ double wg_sum1(Ctx<R> &c, double v)
+{
+    const int lane = c.tid & 63, wv = c.tid >> 6;
+    const double s = wave_sum(v);
+    if (lane == 0) c.S.wred[0][wv] = s;
+    __syncthreads();
+    double t = 0;
+    for (int w = 0; w < kWG / 64; ++w) t += c.S.wred[0][w];
+    __syncthreads();
+    return t;
+}
+
+// ----------------------------------------------------------- tile I/O
+template <class R>
+__device__ __forceinline__ uint64_t tile_base(const PassInfo &pi, int n, int k, uint32_t t)
+{
+    uint64_t base = 0;
+    for (int i = 0; i < n - k; ++i) base |= (uint64_t)((t >> i) & 1u) << pi.gq[i];
+    return base;
+}
+
+template <class R>
+__device__ void build_hi_off(Ctx<R> &c, const PassInfo &pi, int k)
+{
+    const uint32_t nh = 1u << (k - kCoalesceQ);
+    for (uint32_t h = c.tid; h < nh; h += kWG) {
+        uint32_t off = 0;
+        for (int i = 0; i < k - kCoalesceQ; ++i)
+            off |= ((h >> i) & 1u) << pi.tq[kCoalesceQ + i];
+        c.hi_off[h] = off;
+    }
+    __syncthreads();
+}
+
+template <class R>
+__device__ void load_tile(Ctx<R> &c, const typename V2<R>::T *G, uint64_t base, bool fresh)
+{
+    using A = typename V2<R>::T;
+    constexpr uint32_t V = 16 / sizeof(A);
+    for (uint32_t ch = c.tid; ch < c.tsize / V; ch += kWG) {
+        const uint32_t l = ch * V;
+        const uint64_t g = base + c.hi_off[l >> 4] + (l & 15u);
+        if (fresh) {
+#pragma unroll
+            for (uint32_t v = 0; v < V; ++v) {
+                A z;
+                z.x = (g + v == 0) ? (R)1 : (R)0;
+                z.y = 0;
+                c.L[l + v] = z;
+            }
+        } else {
+            *(uint4 *)(c.L + l) = *(const uint4 *)(G + g);
+        }
+    }
+    __syncthreads();
+}
+
+template <class R>
+__device__ void store_tile(Ctx<R> &c, typename V2<R>::T *G, uint64_t base)
+{
+    using A = typename V2<R>::T;
+    constexpr uint32_t V = 16 / sizeof(A);
+    for (uint32_t ch = c.tid; ch < c.tsize / V; ch += kWG) {
+        const uint32_t l = ch * V;
+        const uint64_t g = base + c.hi_off[l >> 4] + (l & 15u);
+        *(uint4 *)(G + g) = *(const uint4 *)(c.L + l);
+    }
+    __syncthreads();
+}
+
+template <class R>
+__device__ __forceinline__ typename V2<R>::T *slot_ptr(const ExecParams &P, int slot)
+{
+    using A = typename V2<R>::T;
+    return (A *)P.slots + (size_t)slot * P.slot_amps;
+}
+
+// ----------------------------------------------------------- queue/slots
+__device__ bool spin_expired(unsigned long long t0, unsigned long long limit)
+{
+    return wall_clock64() - t0 > limit;
+}
+
+// Thread 0 only.
+__device__ int slot_pop(const ExecParams &P)
+{
+    Control *ctl = P.ctl;
+    const unsigned long long t0 = wall_clock64();
+    while (atomicCAS(&ctl->lock, 0u, 1u) != 0u) {
+        __builtin_amdgcn_s_sleep(2);
+        if (spin_expired(t0, P.spin_limit)) {
+            atomicOr(&ctl->error, kErrLock);
+            return -1;
+        }
+    }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    int s = -1;
+    const int top = __hip_atomic_load(&ctl->free_top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (top > 0) {
+        s = __hip_atomic_load(&P.free_slots[top - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->free_top, top - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __hip_atomic_store(&ctl->lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return s;
+}
+
+__device__ void slot_push(const ExecParams &P, int s)
+{
+    Control *ctl = P.ctl;
+    const unsigned long long t0 = wall_clock64();
+    while (atomicCAS(&ctl->lock, 0u, 1u) != 0u) {
+        __builtin_amdgcn_s_sleep(2);
+        if (spin_expired(t0, P.spin_limit)) {
+            atomicOr(&ctl->error, kErrLock);
+            return;
+        }
+    }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    const int top = __hip_atomic_load(&ctl->free_top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (top < P.n_slots) {
+        __hip_atomic_store(&P.free_slots[top], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->free_top, top + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        atomicOr(&ctl->error, kErrState);
+    }
+    __hip_atomic_store(&ctl->lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 only: reserve a record, fill it, publish it.
+__device__ void queue_push(const ExecParams &P, const BranchRec &r)
+{
+    Control *ctl = P.ctl;
+    const uint32_t idx = atomicAdd(&ctl->q_tail, 1u);
+    if (idx >= (uint32_t)P.queue_cap) {
+        atomicOr(&ctl->error, kErrQueue);
+        return;
+    }
+    atomicAdd(&ctl->outstanding, 1);
+    P.queue[idx] = r;
+    __threadfence();
+    st_rel(&P.ready[idx], 1u);
+}
+
+// ----------------------------------------------------------- decisions
+__device__ __forceinline__ int pauli_pick(const ExecParams &P, const DevRule &ru, double u)
+{
+    const double *thr = P.pool + ru.thr;
+    for (int j = 0; j < (int)ru.n_terms; ++j)
+        if (u < thr[j]) return j;
+    return (int)ru.n_terms - 1;
+}
+
+// First candidate whose running sum of S.red[1..] exceeds u*N; if rounding
+// leaves none, the last candidate with a non-zero weight.
+__device__ __forceinline__ int red_pick(const WgShared &S, int cnt, double u)
+{
+    const double x = u * S.red[0];
+    double run = 0;
+    int last = -1;
+    for (int o = 0; o < cnt; ++o) {
+        const double p = S.red[1 + o];
+        if (p > 0) last = o;
+        run += p;
+        if (x < run) return o;
+    }
+    return last < 0 ? 0 : last;
+}
+
+__device__ __forceinline__ int red_count(const ExecParams &P, const DevOp &op)
+{
+    return op.kind == DK_KRAUS ? (int)P.rules[op.rule].n_terms : (1 << op.nq);
+}
+
+// Record measured bits (with readout flips) of shot `shot`.
+__device__ void record_bits(const ExecParams &P, const DevOp &op, uint64_t shot, uint32_t o)
+{
+    uint64_t m = P.memory[shot];
+    for (int t = 0; t < op.nq; ++t) {
+        uint64_t bit = (o >> t) & 1u;
+        const double pf = bit ? P.ro10 : P.ro01;
+        if (pf > 0 && philox_u01(P.seed, shot, op.r, 1u + t) < pf) bit ^= 1u;
+        m = (m & ~(1ull << op.c[t])) | (bit << op.c[t]);
+    }
+    P.memory[shot] = m;
+}
+
+// Outcome of shot `shot` at random op `op` (after its reduction, if any).
+__device__ __forceinline__ int outcome_of(const ExecParams &P, const WgShared &S,
+                                          const DevOp &op, uint64_t shot)
+{
+    const double u = philox_u01(P.seed, shot, op.r, 0);
+    if (op.kind == DK_PAULI) return pauli_pick(P, P.rules[op.rule], u);
+    return red_pick(S, red_count(P, op), u);
+}
+
+// ----------------------------------------------------------- the kernel
+template <class R>
+__device__ void copy_state_to_slot(Ctx<R> &c, int dst, int src_slot, bool from_lds)
+{
+    using A = typename V2<R>::T;
+    const ExecParams &P = c.P;
+    A *D = slot_ptr<R>(P, dst);
+    const uint64_t namps = 1ull << P.n_qubits;
+    if (from_lds) {
+        for (uint64_t i = c.tid; i < namps; i += kWG) D[i] = c.L[i];
+    } else {
+        const uint4 *Sp = (const uint4 *)slot_ptr<R>(P, src_slot);
+        uint4 *Dp = (uint4 *)D;
+        const uint64_t n16 = namps * sizeof(A) / 16;
+        for (uint64_t i = c.tid; i < n16; i += kWG) Dp[i] = Sp[i];
+    }
+    __threadfence();
+    __syncthreads();
+}
+
+// Partition the branch's shots by outcome at op j and continue with the
+// first group; other groups get a copied state (or the waiting list).
+template <class R>
+__device__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
+{
+    const ExecParams &P = c.P;
+    WgShared &S = c.S;
+    const int tid = c.tid;
+    const int m = S.hi - S.lo;
+    const int chunk = (m + kWG - 1) / kWG;
+    const int my_lo = S.lo + min(m, tid * chunk), my_hi = S.lo + min(m, (tid + 1) * chunk);
+    int my_cnt[16];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) my_cnt[o] = 0;
+    for (int i = my_lo; i < my_hi; ++i) {
+        const int o = outcome_of(P, S, op, (uint64_t)P.shot_perm[i]);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) my_cnt[q] += (o == q);
+    }
+#pragma unroll
+    for (int o = 0; o < 16; ++o) c.cnt[o * kWG + tid] = my_cnt[o];
+    __syncthreads();
+    if (tid < 16) {  // exclusive scan of row `tid` over threads
+        int run = 0;
+        for (int t = 0; t < kWG; ++t) {
+            const int v = c.cnt[tid * kWG + t];
+            c.cnt[tid * kWG + t] = run;
+            run += v;
+        }
+        S.tot[tid] = run;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int off = S.lo, g = 0;
+        for (int o = 0; o < 16; ++o) {
+            if (S.tot[o] == 0) continue;
+            S.grp_o[g] = o;
+            S.grp_lo[g] = off;
+            S.grp_hi[g] = off + S.tot[o];
+            off += S.tot[o];
+            ++g;
+        }
+        S.n_groups = g;
+    }
+    __syncthreads();
+    // scatter into shot_tmp, then copy back
+    {
+        int pos[16];
+        for (int o = 0; o < 16; ++o) {
+            int base = 0;
+            for (int g = 0; g < S.n_groups; ++g)
+                if (S.grp_o[g] == o) base = S.grp_lo[g];
+            pos[o] = base + c.cnt[o * kWG + tid];
+        }
+        for (int i = my_lo; i < my_hi; ++i) {
+            const int shot = P.shot_perm[i];
+            const int o = outcome_of(P, S, op, (uint64_t)shot);
+            int p = 0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (o == q) p = pos[q]++;
+            P.shot_tmp[p] = shot;
+            if (op.kind == DK_MEASURE && (op.flags & DF_RECORD))
+                record_bits(P, op, (uint64_t)shot, (uint32_t)o);
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int i = S.lo + tid; i < S.hi; i += kWG) P.shot_perm[i] = P.shot_tmp[i];
+    __syncthreads();
+
+    const bool measure_like = op.kind != DK_PAULI;
+    for (int g = 1; g < S.n_groups; ++g) {
+        const int o = S.grp_o[g];
+        const double sc = measure_like ? 1.0 / sqrt(S.red[1 + o]) : 1.0;
+        if (tid == 0) S.alloc_slot = slot_pop(P);
+        __syncthreads();
+        const int slot = S.alloc_slot;
+        // a parent that was never written is still |0..0>: no copy needed
+        const bool child_fresh = S.fresh && !P.resident;
+        if (slot >= 0) {
+            if (!child_fresh) copy_state_to_slot(c, slot, S.slot, P.resident != 0);
+            if (tid == 0) {
+                BranchRec r;
+                r.slot = slot;
+                r.lo = S.grp_lo[g];
+                r.hi = S.grp_hi[g];
+                r.cursor = j;
+                r.pending = o;
+                r.flags = child_fresh ? 1 : 0;
+                r.scale = sc;
+                r.norm_lb = measure_like ? 1.0 : S.norm_lb;
+                S.st[ST_BRANCHES] += 1;
+                queue_push(P, r);
+            }
+        } else {
+            const int cntg = S.grp_hi[g] - S.grp_lo[g];
+            if (tid == 0) {
+                S.wait_base = (int)atomicAdd(&P.ctl->wait_count, (uint32_t)cntg);
+                S.st[ST_WAITING] += cntg;
+            }
+            __syncthreads();
+            for (int i = tid; i < cntg; i += kWG) P.waiting[S.wait_base + i] = P.shot_perm[S.grp_lo[g] + i];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int o = S.grp_o[0];
+        S.lo = S.grp_lo[0];
+        S.hi = S.grp_hi[0];
+        S.cursor = j;
+        S.pending = o;
+        S.first_scale = measure_like ? 1.0 / sqrt(S.red[1 + o]) : 1.0;
+        if (measure_like) S.norm_lb = 1.0;
+        S.st[ST_SPLITS] += 1;
+    }
+    __syncthreads();
+}
+
+// Determine the op range of the next sweep (and why it stops).
+template <class R>
+__device__ void plan_pass(Ctx<R> &c)
+{
+    const ExecParams &P = c.P;
+    WgShared &S = c.S;
+    const int tid = c.tid;
+    const int start = S.cursor;
+    const int m = S.hi - S.lo;
+    int j = start;
+    if (start >= P.n_ops) {
+        if (tid == 0) { S.start = S.end = start; S.stop = STOP_END; }
+        __syncthreads();
+        return;
+    }
+    const PassInfo &pi = P.passes[P.ops[start].pass];
+    const int end_static = (int)pi.end_op;
+    if (S.pending >= 0) {
+        if (tid == 0) c.dec[0] = S.pending;
+        ++j;
+    }
+    double nlb = S.norm_lb;
+    int stop = STOP_NONE;
+    const double lb_floor = sizeof(R) == 4 ? 0x1.0p-30 : 0x1.0p-200;
+    for (;;) {
+        while (j < end_static && j - start < kMaxPassOps) {
+            const uint16_t kd = P.ops[j].kind;
+            if (kd == DK_PAULI || kd == DK_KRAUS || kd == DK_MEASURE) break;
+            ++j;
+        }
+        if (j >= end_static || j - start >= kMaxPassOps) break;
+        const DevOp &op = P.ops[j];
+        if (op.kind == DK_MEASURE) {
+            stop = (op.flags & DF_TERMINAL) ? STOP_TERMINAL : STOP_REDUCE;
+            break;
+        }
+        const DevRule &ru = P.rules[op.rule];
+        if (m == 1) {
+            // every thread evaluates the single shot's draw (no barrier)
+            const uint64_t shot = (uint64_t)P.shot_perm[S.lo];
+            const double u = philox_u01(P.seed, shot, op.r, 0);
+            if (op.kind == DK_PAULI) {
+                if (tid == 0) c.dec[j - start] = pauli_pick(P, ru, u);
+                ++j;
+                continue;
+            }
+            if (u < ru.lam_min0 && nlb * ru.lam_min0 >= lb_floor) {
+                if (tid == 0) c.dec[j - start] = 0;
+                nlb *= ru.lam_min0;
+                ++j;
+                continue;
+            }
+            stop = STOP_REDUCE;
+            break;
+        }
+        // several shots: evaluate all draws, agree on the outcome
+        if (tid == 0) { S.omin = 1 << 30; S.omax = -1; S.anyhigh = 0; }
+        __syncthreads();
+        int lmin = 1 << 30, lmax = -1, high = 0;
+        for (int i = S.lo + tid; i < S.hi; i += kWG) {
+            const uint64_t shot = (uint64_t)P.shot_perm[i];
+            const double u = philox_u01(P.seed, shot, op.r, 0);
+            if (op.kind == DK_PAULI) {
+                const int o = pauli_pick(P, ru, u);
+                lmin = min(lmin, o);
+                lmax = max(lmax, o);
+            } else if (!(u < ru.lam_min0)) {
+                high = 1;
+            }
+        }
+        if (op.kind == DK_PAULI) {
+            atomicMin(&S.omin, lmin);
+            atomicMax(&S.omax, lmax);
+        } else if (high) {
+            atomicOr(&S.anyhigh, 1);
+        }
+        __syncthreads();
+        const int omin = S.omin, omax = S.omax, anyhigh = S.anyhigh;
+        __syncthreads();
+        if (op.kind == DK_PAULI) {
+            if (omin == omax) {
+                if (tid == 0) c.dec[j - start] = omin;
+                ++j;
+                continue;
+            }
+            stop = STOP_SPLIT;
+            break;
+        }
+        if (!anyhigh && nlb * ru.lam_min0 >= lb_floor) {
+            if (tid == 0) c.dec[j - start] = 0;
+            nlb *= ru.lam_min0;
+            ++j;
+            continue;
+        }
+        stop = STOP_REDUCE;
+        break;
+    }
+    if (tid == 0) {
+        S.start = start;
+        S.end = j;
+        S.stop = stop;
+        S.stop_op = j;
+        S.norm_lb = nlb;
+    }
+    __syncthreads();
+}
+
+template <class R>
+__device__ void apply_range(Ctx<R> &c, uint64_t &flops)
+{
+    const ExecParams &P = c.P;
+    WgShared &S = c.S;
+    for (int j = S.start; j < S.end; ++j) {
+        const DevOp &op = P.ops[j];
+        const int d = c.dec[j - S.start];
+        const double s = (j == S.start && S.pending >= 0) ? S.first_scale : 1.0;
+        apply_op(c, op, d, s);
+        flops += op_flops(P, op, d);
+    }
+}
+
+// One sweep over the state: apply [start, end), then accumulate the
+// reduction of the stopping op if asked.
+template <class R>
+__device__ void run_sweep(Ctx<R> &c, bool want_reduce)
+{
+    using A = typename V2<R>::T;
+    const ExecParams &P = c.P;
+    WgShared &S = c.S;
+    const int n = P.n_qubits, k = P.tile_q;
+    const bool has_ops = S.end > S.start;
+    double acc[kMaxRed];
+#pragma unroll
+    for (int v = 0; v < kMaxRed; ++v) acc[v] = 0;
+    const DevOp &rop = P.ops[S.stop_op < P.n_ops ? S.stop_op : 0];
+    uint64_t flops = 0;
+    if (P.resident) {
+        apply_range(c, flops);
+        if (want_reduce) reduce_tile(c, rop, acc);
+    } else {
+        const PassInfo &pi = P.passes[P.ops[S.start].pass];
+        build_hi_off(c, pi, k);
+        A *G = slot_ptr<R>(P, S.slot);
+        const bool fresh = S.fresh != 0;
+        for (uint32_t t = 0; t < c.n_tiles; ++t) {
+            const uint64_t base = tile_base<R>(pi, n, k, t);
+            load_tile(c, G, base, fresh);
+            apply_range(c, flops);
+            if (want_reduce) {
+                reduce_tile(c, rop, acc);
+            }
+            if (has_ops) store_tile(c, G, base);
+        }
+        if (c.tid == 0) {
+            const uint64_t sb = (1ull << n) * sizeof(A);
+            S.st[ST_PASSES] += 1;
+            S.st[ST_BYTES] += (fresh ? 0 : sb) + (has_ops ? sb : 0);
+        }
+        if (has_ops) {
+            __syncthreads();
+            if (c.tid == 0) S.fresh = 0;
+        }
+    }
+    if (c.tid == 0) S.st[ST_FLOPS] += flops * (uint64_t)c.tsize;
+    if (want_reduce) {
+        wg_reduce(c, acc, 1 + red_count(P, rop));
+        if (c.tid == 0) S.st[ST_REDUCTIONS] += 1;
+    }
+    __syncthreads();
+}
+
+// After a reduction for op j: each shot's outcome; continue with it, or
+// split the branch.
+template <class R>
+__device__ void decide(Ctx<R> &c)
+{
+    const ExecParams &P = c.P;
+    WgShared &S = c.S;
+    const int j = S.stop_op;
+    const DevOp &op = P.ops[j];
+    const int m = S.hi - S.lo;
+    if (m == 1) {
+        if (c.tid == 0) {
+            const uint64_t shot = (uint64_t)P.shot_perm[S.lo];
+            const int o = outcome_of(P, S, op, shot);
+            if (op.kind == DK_MEASURE && (op.flags & DF_RECORD)) record_bits(P, op, shot, (uint32_t)o);
+            S.cursor = j;
+            S.pending = o;
+            S.first_scale = 1.0 / sqrt(S.red[1 + o]);
+            S.norm_lb = 1.0;
+        }
+        __syncthreads();
+        return;
+    }
+    if (P.branch_mode) {
+        split_branch(c, op, j);
+        return;
+    }
+    // several shots on one state without splitting cannot happen
+    if (c.tid == 0) {
+        atomicOr(&P.ctl->error, kErrState);
+        S.cursor = P.n_ops;
+        S.pending = -1;
+    }
+    __syncthreads();
+}
+
+// Final measurement of all qubits by sampling the shared state once per
+// shot: FP64 tile sums, tile search, in-tile prefix and search.
+template <class R>
+__device__ void terminal_sample(Ctx<R> &c)
+{
+    using A = typename V2<R>::T;
+    const ExecParams &P = c.P;
+    WgShared &S = c.S;
+    const int n = P.n_qubits, k = P.tile_q;
+    const int tid = c.tid;
+    const DevOp &op = P.ops[S.stop_op];
+    double *D = (double *)c.L;  // in-place |a|^2 prefix, same bytes as the tile
+    double *tsums = P.tile_sums + (size_t)blockIdx.x * c.n_tiles;
+    const PassInfo &pi = P.passes[op.pass];
+    A *G = P.resident ? nullptr : slot_ptr<R>(P, S.slot);
+    const uint32_t seg = c.tsize >= kWG ? c.tsize / kWG : 1;
+
+    // in-tile: D[e] = inclusive prefix of |a|^2 in the tile (LDS)
+    auto tile_prefix = [&](void) {
+        double vals[32];
+        const uint32_t my0 = tid * seg;
+        const bool active = my0 < c.tsize;
+        double run = 0;
+        if (sizeof(A) == 8) {
+            if (active)
+                for (uint32_t e = 0; e < seg; ++e) {
+                    run += abs2d(c.L[my0 + e]);
+                    D[my0 + e] = run;
+                }
+            __syncthreads();
+        } else {
+            // 16-byte amplitudes overlap other threads' doubles: read first
+            for (uint32_t e0 = 0; e0 < seg; e0 += 32) {
+                const uint32_t cntv = min(32u, seg - e0);
+                if (active)
+                    for (uint32_t e = 0; e < cntv; ++e) vals[e] = abs2d(c.L[my0 + e0 + e]);
+                __syncthreads();
+                if (active)
+                    for (uint32_t e = 0; e < cntv; ++e) {
+                        run += vals[e];
+                        D[my0 + e0 + e] = run;
+                    }
+                __syncthreads();
+            }
+        }
+        // segment offsets (sequential over segments, fixed order)
+        double *off = (double *)c.cnt;   // kWG doubles
+        if (active) off[tid] = run; else if (tid < kWG) off[tid] = 0;
+        __syncthreads();
+        if (tid == 0) {
+            double r2 = 0;
+            for (int t = 0; t < kWG; ++t) {
+                const double v = off[t];
+                off[t] = r2;
+                r2 += v;
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const double o = off[tid];
+            for (uint32_t e = 0; e < seg; ++e) D[my0 + e] += o;
+        }
+        __syncthreads();
+    };
+
+    if (P.resident) {
+        tile_prefix();
+        if (tid == 0) { tsums[0] = D[c.tsize - 1]; }
+        __syncthreads();
+    } else {
+        build_hi_off(c, pi, k);
+        for (uint32_t t = 0; t < c.n_tiles; ++t) {
+            const uint64_t base = tile_base<R>(pi, n, k, t);
+            load_tile(c, G, base, S.fresh != 0);
+            double a = 0;
+            for (uint32_t i = tid; i < c.tsize; i += kWG) a += abs2d(c.L[i]);
+            const double s = wg_sum1(c, a);
+            if (tid == 0) tsums[t] = s;
+        }
+        if (tid == 0) {
+            S.st[ST_PASSES] += 1;
+            S.st[ST_BYTES] += S.fresh ? 0 : (1ull << n) * sizeof(A);
+            double r2 = 0;  // tile sums -> inclusive prefix
+            for (uint32_t t = 0; t < c.n_tiles; ++t) {
+                r2 += tsums[t];
+                tsums[t] = r2;
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    const double N = tsums[c.n_tiles - 1];
+    // tile of each shot -> shot_tmp[i]
+    for (int i = S.lo + tid; i < S.hi; i += kWG) {
+        const uint64_t shot = (uint64_t)P.shot_perm[i];
+        const double x = philox_u01(P.seed, shot, op.r, 0) * N;
+        int t = -1;
+        uint32_t lo = 0, hi = c.n_tiles;  // first t with x < tsums[t]
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (x < tsums[mid]) hi = mid; else lo = mid + 1;
+        }
+        if (lo < c.n_tiles) {
+            t = (int)lo;
+        } else {  // rounding: last tile with weight
+            for (int tt = (int)c.n_tiles - 1; tt >= 0; --tt) {
+                const double prev = tt ? tsums[tt - 1] : 0.0;
+                if (tsums[tt] > prev) { t = tt; break; }
+            }
+            if (t < 0) t = 0;
+        }
+        P.shot_tmp[i] = t;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (uint32_t t = 0; t < c.n_tiles; ++t) {
+        // does any shot land in tile t?
+        if (tid == 0) S.anyhigh = 0;
+        __syncthreads();
+        for (int i = S.lo + tid; i < S.hi; i += kWG)
+            if (P.shot_tmp[i] == (int)t) { S.anyhigh = 1; break; }
+        __syncthreads();
+        const int hit = S.anyhigh;
+        __syncthreads();
+        if (!hit) continue;
+        if (!P.resident) {
+            load_tile(c, G, (uint64_t)t << k, S.fresh != 0);
+            tile_prefix();
+        }
+        const double excl = t ? tsums[t - 1] : 0.0;
+        for (int i = S.lo + tid; i < S.hi; i += kWG) {
+            if (P.shot_tmp[i] != (int)t) continue;
+            const uint64_t shot = (uint64_t)P.shot_perm[i];
+            const double x = philox_u01(P.seed, shot, op.r, 0) * N;
+            uint32_t lo = 0, hi = c.tsize;  // first e with x < excl + D[e]
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (x < excl + D[mid]) hi = mid; else lo = mid + 1;
+            }
+            uint32_t e = lo;
+            if (e >= c.tsize) {  // rounding: last non-zero entry of the tile
+                e = c.tsize - 1;
+                while (e > 0 && !(D[e] > D[e - 1])) --e;
+            }
+            const uint64_t idx = ((uint64_t)t << k) | e;
+            uint64_t mm = P.memory[shot];
+            for (int q = 0; q < n; ++q) {
+                uint64_t bit = (idx >> q) & 1u;
+                const double pf = bit ? P.ro10 : P.ro01;
+                if (pf > 0 && philox_u01(P.seed, shot, op.r, 1u + q) < pf) bit ^= 1u;
+                mm = (mm & ~(1ull << op.c[q])) | (bit << op.c[q]);
+            }
+            P.memory[shot] = mm;
+        }
+        __syncthreads();
+    }
+}
+
+// Write the normalised state of this branch into P.dump (complex double).
+template <class R>
+__device__ void dump_state(Ctx<R> &c, const PassInfo &pi)
+{
+    using A = typename V2<R>::T;
+    const ExecParams &P = c.P;
+    WgShared &S = c.S;
+    const int n = P.n_qubits, k = P.tile_q;
+    double2 *out = (double2 *)P.dump;
+    double a = 0;
+    if (P.resident) {
+        for (uint32_t i = c.tid; i < c.tsize; i += kWG) a += abs2d(c.L[i]);
+        const double N = wg_sum1(c, a);
+        const double f = 1.0 / sqrt(N);
+        for (uint32_t i = c.tid; i < c.tsize; i += kWG) {
+            const A v = c.L[i];
+            out[i] = make_double2((double)v.x * f, (double)v.y * f);
+        }
+        __syncthreads();
+        return;
+    }
+    A *G = slot_ptr<R>(P, S.slot);
+    build_hi_off(c, pi, k);
+    for (uint32_t t = 0; t < c.n_tiles; ++t) {
+        load_tile(c, G, tile_base<R>(pi, n, k, t), S.fresh != 0);
+        for (uint32_t i = c.tid; i < c.tsize; i += kWG) a += abs2d(c.L[i]);
+        __syncthreads();
+    }
+    const double N = wg_sum1(c, a);
+    const double f = 1.0 / sqrt(N);
+    for (uint32_t t = 0; t < c.n_tiles; ++t) {
+        const uint64_t base = tile_base<R>(pi, n, k, t);
+        load_tile(c, G, base, S.fresh != 0);
+        for (uint32_t l = c.tid; l < c.tsize; l += kWG) {
+            const uint64_t g = base + c.hi_off[l >> 4] + (l & 15u);
+            const A v = c.L[l];
+            out[g] = make_double2((double)v.x * f, (double)v.y * f);
+        }
+        __syncthreads();
+    }
+}
+
+template <class R>
+__device__ void maybe_dump(Ctx<R> &c, int at_op)
+{
+    const ExecParams &P = c.P;
+    WgShared &S = c.S;
+    if (P.dump_shot < 0 || P.dump == nullptr) return;
+    if (c.tid == 0) S.dump_here = 0;
+    __syncthreads();
+    for (int i = S.lo + c.tid; i < S.hi; i += kWG)
+        if ((int64_t)P.shot_perm[i] == P.dump_shot) S.dump_here = 1;
+    __syncthreads();
+    if (!S.dump_here) return;
+    const int pidx = P.ops[at_op < P.n_ops ? at_op : P.n_ops - 1].pass;
+    dump_state(c, P.passes[pidx]);
+}
+
+template <class R>
+__global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
+{
+    using A = typename V2<R>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ WgShared S;
+    const int tid = threadIdx.x;
+    const int n = P.n_qubits, k = P.tile_q;
+    Ctx<R> c{P, S};
+    c.tid = tid;
+    c.tsize = 1u << k;
+    c.n_tiles = P.resident ? 1u : (1u << (n - k));
+    c.L = (A *)smem;
+    c.hi_off = (uint32_t *)(smem + (size_t)c.tsize * sizeof(A));
+    const uint32_t n_hi = P.resident ? 4u : (1u << (k - kCoalesceQ));
+    c.dec = (int *)(c.hi_off + n_hi);
+    c.cnt = c.dec + kMaxPassOps;
+    if (tid < ST_COUNT) S.st[tid] = 0;
+    __syncthreads();
+
+    for (;;) {
+        if (tid == 0) {
+            S.status = ST_EXIT;
+            Control *ctl = P.ctl;
+            if (ld_rlx(&ctl->error) == 0) {
+                const uint32_t t = atomicAdd(&ctl->q_head, 1u);
+                if (t < (uint32_t)P.queue_cap && (P.branch_mode || t < ctl->n_initial)) {
+                    const unsigned long long t0 = wall_clock64();
+                    for (;;) {
+                        // poll relaxed; one acquire fence once the record is published
+                        if (ld_rlx(&P.ready[t])) {
+                            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+                            S.rec = P.queue[t];
+                            S.status = ST_WORK;
+                            break;
+                        }
+                        if (ld_rlx_i(&ctl->outstanding) <= 0) break;
+                        if (spin_expired(t0, P.spin_limit)) {
+                            atomicOr(&ctl->error, kErrTimeout);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(8);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (S.status == ST_EXIT) break;
+
+        // ---- set up the branch's state
+        if (tid == 0) {
+            S.lo = S.rec.lo;
+            S.hi = S.rec.hi;
+            S.cursor = S.rec.cursor;
+            S.pending = S.rec.pending;
+            S.first_scale = S.rec.scale;
+            S.norm_lb = S.rec.norm_lb;
+            if (P.resident) {
+                S.slot = S.rec.slot;
+                S.fresh = (S.rec.slot < 0) || (S.rec.flags & 1);
+            } else if (P.private_slots) {
+                S.slot = blockIdx.x;
+                S.fresh = 1;
+            } else {
+                S.slot = S.rec.slot;
+                S.fresh = S.rec.flags & 1;
+            }
+        }
+        __syncthreads();
+        if (P.resident) {
+            if (S.fresh) {
+                for (uint32_t i = tid; i < c.tsize; i += kWG) {
+                    A z;
+                    z.x = (i == 0) ? (R)1 : (R)0;
+                    z.y = 0;
+                    c.L[i] = z;
+                }
+            } else {
+                const A *G = slot_ptr<R>(P, S.slot);
+                for (uint32_t i = tid; i < c.tsize; i += kWG) c.L[i] = G[i];
+            }
+            __syncthreads();
+            if (S.slot >= 0 && tid == 0) slot_push(P, S.slot);
+            if (tid == 0) { S.slot = -1; S.fresh = 0; }
+            __syncthreads();
+        }
+
+        // ---- run the op list
+        for (;;) {
+            plan_pass(c);
+            const int stop = S.stop;
+            if (stop == STOP_TERMINAL || stop == STOP_END) {
+                if (S.end > S.start) run_sweep(c, false);
+                if (tid == 0) { S.cursor = S.end; S.pending = -1; }
+                __syncthreads();
+                maybe_dump(c, S.cursor);
+                if (stop == STOP_TERMINAL) {
+                    if (tid == 0) S.stop_op = S.cursor;
+                    __syncthreads();
+                    terminal_sample(c);
+                }
+                break;
+            }
+            if (stop == STOP_NONE && S.end == S.start) {  // no progress: give up
+                if (tid == 0) atomicOr(&P.ctl->error, kErrState);
+                break;
+            }
+            if (S.end > S.start || stop == STOP_REDUCE) run_sweep(c, stop == STOP_REDUCE);
+            if (stop == STOP_NONE) {
+                if (tid == 0) { S.cursor = S.end; S.pending = -1; }
+                __syncthreads();
+                continue;
+            }
+            if (stop == STOP_REDUCE) {
+                decide(c);
+                continue;
+            }
+            // STOP_SPLIT on a Pauli channel
+            split_branch(c, P.ops[S.stop_op], S.stop_op);
+        }
+
+        // ---- release the state and finish the record
+        __syncthreads();
+        if (tid == 0) {
+            if (!P.resident && !P.private_slots && S.slot >= 0) slot_push(P, S.slot);
+            __threadfence();
+            atomicSub(&P.ctl->outstanding, 1);
+        }
+        __syncthreads();
+    }
+    if (tid < ST_COUNT) atomicAdd(&P.ctl->stat[tid], S.st[tid]);
+}
+
+// Prepare one run (or one waiting-list relaunch).
+__global__ void init_kernel(ExecParams P, int restart, int n_root_shots, int root_slot,
+                            int n_free)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int n_initial = P.branch_mode ? 1 : (int)P.n_shots;
+    for (int64_t i = gid; i < P.n_shots; i += stride) {
+        if (!restart) {
+            P.memory[i] = 0;
+            P.shot_perm[i] = (int32_t)i;
+        }
+    }
+    for (int64_t i = gid; i < P.queue_cap; i += stride) {
+        if (i < n_initial) {
+            BranchRec r;
+            if (P.branch_mode) {
+                r.slot = root_slot;
+                r.lo = 0;
+                r.hi = n_root_shots;
+            } else {
+                r.slot = -1;
+                r.lo = (int32_t)i;
+                r.hi = (int32_t)i + 1;
+            }
+            r.cursor = 0;
+            r.pending = -1;
+            r.flags = 1;
+            r.scale = 1.0;
+            r.norm_lb = 1.0;
+            P.queue[i] = r;
+            P.ready[i] = 1u;
+        } else {
+            P.ready[i] = 0u;
+        }
+    }
+    for (int64_t i = gid; i < n_free; i += stride) {
+        // free stack: every slot except the root's
+        P.free_slots[i] = (int32_t)((root_slot < 0 || i < root_slot) ? i : i + 1);
+    }
+    if (gid == 0) {
+        Control *ctl = P.ctl;
+        ctl->q_head = 0;
+        ctl->q_tail = n_initial;
+        ctl->outstanding = n_initial;
+        ctl->error = 0;
+        ctl->lock = 0;
+        ctl->free_top = n_free;
+        ctl->wait_count = 0;
+        ctl->n_initial = n_initial;
+        for (int s = 0; s < ST_COUNT; ++s) ctl->stat[s] = 0;
+        ctl->done_workers = 0;
+    }
+}
+
+// Waiting-list relaunch: the parked shots become the root's range and
+// their registers are cleared.
+__global__ void restart_kernel(ExecParams P, int n_wait)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gid; i < n_wait; i += stride) {
+        const int32_t s = P.waiting[i];
+        P.shot_perm[i] = s;
+        P.memory[s] = 0;
+    }
+}
+
+}  // namespace svb
+
+// ------------------------------------------------------------ launchers
+extern "C" {
+
+hipError_t svb_launch_init(const svb::ExecParams *P, int restart, int n_root, int root_slot,
+                           int n_free, hipStream_t st)
+{
+    hipLaunchKernelGGL(svb::init_kernel, dim3(1024), dim3(256), 0, st, *P, restart, n_root,
+                       root_slot, n_free);
+    return hipGetLastError();
+}
+
+hipError_t svb_launch_restart(const svb::ExecParams *P, int n_wait, hipStream_t st)
+{
+    hipLaunchKernelGGL(svb::restart_kernel, dim3(256), dim3(256), 0, st, *P, n_wait);
+    return hipGetLastError();
+}
+
+size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident)
+{
+    const size_t tile = ((size_t)1 << tile_q) * amp_bytes;
+    const size_t hi = resident ? 4 * 4 : ((size_t)1 << (tile_q - svb::kCoalesceQ)) * 4;
+    const size_t dec = svb::kMaxPassOps * 4;
+    const size_t cnt = 16 * svb::kWG * 4;
+    return tile + hi + dec + cnt;
+}
+
+hipError_t svb_launch_exec(const svb::ExecParams *P, int is_c128, int workers, hipStream_t st)
+{
+    const size_t lds = svb_exec_lds_bytes(P->tile_q, is_c128 ? 16 : 8, P->resident);
+    if (is_c128) {
+        hipError_t e = hipFuncSetAttribute((const void *)svb::exec_kernel<double>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(svb::exec_kernel<double>, dim3(workers), dim3(svb::kWG), lds, st, *P);
+    } else {
+        hipError_t e = hipFuncSetAttribute((const void *)svb::exec_kernel<float>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(svb::exec_kernel<float>, dim3(workers), dim3(svb::kWG), lds, st, *P);
+    }
+    return hipGetLastError();
+}
+
+hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int *blocks_per_cu)
+{
+    const size_t lds = svb_exec_lds_bytes(tile_q, is_c128 ? 16 : 8, resident);
+    hipError_t e;
+    if (is_c128) {
+        e = hipFuncSetAttribute((const void *)svb::exec_kernel<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, svb::exec_kernel<double>,
+                                                         svb::kWG, lds);
+    } else {
+        e = hipFuncSetAttribute((const void *)svb::exec_kernel<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, svb::exec_kernel<float>,
+                                                         svb::kWG, lds);
+    }
+    return e;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Device program of one circuit: op records, static pass plan, parameter
+// pool, and the control/queue records of the persistent executor. Shared by
+// the host runtime (runtime.cpp) and the kernels (kernels.hip).
+#pragma once
+#include <stdint.h>
+
+namespace svb {
+
+constexpr int kWG = 256;             // threads per executor workgroup
+constexpr int kMaxPassOps = 1024;    // ops applied in one tile sweep
+constexpr int kMaxKraus = 8;         // matrices per Kraus channel
+constexpr int kMaxMeasQ = 4;         // qubits of a non-terminal measure
+constexpr int kMaxRed = 1 + 16;      // norm + up to 16 outcome sums
+constexpr int kCoalesceQ = 4;        // low qubits always inside a tile
+constexpr int kMaxTileQ = 14;
+
+// Device op kinds (after noise-site expansion).
+enum DevKind : uint16_t {
+    DK_MAT1 = 1,     // 2x2 matrix on lb[0]
+    DK_MAT2 = 2,     // 4x4 matrix on (lb[0], lb[1]); index bit t <-> lb[t]
+    DK_CX = 3,       // control lb[0], target lb[1]
+    DK_CZ = 4,
+    DK_SWAP = 5,
+    DK_PAULI = 6,    // Pauli channel of rule `rule`
+    DK_KRAUS = 7,    // Kraus channel of rule `rule`
+    DK_MEASURE = 8,  // measure / reset / measure+reset of q[0..nq-1]
+};
+
+enum DevFlags : uint8_t {
+    DF_DIAG = 1,      // DK_MAT1: off-diagonal entries are zero
+    DF_RECORD = 2,    // DK_MEASURE: write clbits
+    DF_RESET = 4,     // DK_MEASURE: return measured 1s to |0>
+    DF_TERMINAL = 8,  // DK_MEASURE: last op, all qubits in order (sampling)
+};
+
+struct DevOp {
+    uint16_t kind;
+    uint8_t nq;
+    uint8_t flags;
+    uint32_t r;          // index in the expanded op list (Philox counter word)
+    uint32_t pass;       // static pass holding this op
+    uint32_t mat;        // pool offset (doubles) of this op's matrix
+    uint32_t rule;       // noise rule index (DK_PAULI / DK_KRAUS)
+    uint32_t pad;
+    uint8_t q[8];        // physical qubits
+    uint8_t lb[8];       // tile-local bit of each qubit in its static pass
+    uint8_t c[32];       // clbits (terminal measure: clbit of qubit t)
+};
+
+// Per-rule channel data in the pool.
+struct DevRule {
+    uint32_t is_kraus;
+    uint32_t nq;
+    uint32_t n_terms;
+    uint32_t thr;        // Pauli: pool offset of cumulative thresholds (doubles)
+    uint32_t mats;       // Kraus: pool offset of matrices (fp64 complex)
+    uint32_t diag_mm;    // Kraus: every K^dagger K is diagonal
+    double lam_min0;     // Kraus: smallest eigenvalue of K0^dagger K0
+    uint32_t xcode[16];  // Pauli term: bit t set if X or Y on gate qubit t
+    uint32_t zcode[16];  // Pauli term: bit t set if Z or Y on gate qubit t
+    uint32_t ny[16];     // Pauli term: number of Y
+    uint32_t ident_mask; // Pauli: bit j set if term j is the identity
+    uint32_t pad2;
+};
+
+struct PassInfo {
+    uint32_t first_op, end_op;  // ops [first_op, end_op)
+    uint32_t tmask;             // physical qubits inside the tile
+    uint32_t contiguous;        // tile qubits are 0..k-1
+    uint8_t tq[16];             // tile qubits, ascending (k entries)
+    uint8_t gq[32];             // remaining qubits, ascending (n-k entries)
+};
+
+// Work-queue record: a state (slot) shared by shots shot_perm[lo..hi).
+struct BranchRec {
+    int32_t slot;       // state slot, -1: none (fresh |0> in LDS)
+    int32_t lo, hi;     // shot range in shot_perm
+    int32_t cursor;     // next op to apply
+    int32_t pending;    // decided outcome of op[cursor], -1: none
+    int32_t flags;      // bit0: slot content is the fresh |0> state (not written)
+    double scale;       // renormalisation applied with the pending op
+    double norm_lb;     // lower bound of the state's squared norm
+};
+
+enum CtlStat {
+    ST_PASSES = 0, ST_BYTES, ST_REDUCTIONS, ST_BRANCHES, ST_WAITING,
+    ST_FLOPS, ST_SPLITS, ST_COUNT
+};
+
+struct Control {
+    uint32_t q_head;        // tickets handed out
+    uint32_t q_tail;        // records reserved
+    int32_t outstanding;    // records pushed and not finished
+    uint32_t error;         // device failure flags (see kErr*)
+    uint32_t lock;          // slot stack lock
+    int32_t free_top;       // free slots on the stack
+    uint32_t wait_count;    // shots on the waiting list
+    uint32_t n_initial;     // records present at launch
+    unsigned long long stat[ST_COUNT];
+    uint32_t done_workers;
+    uint32_t pad[7];
+};
+
+constexpr uint32_t kErrTimeout = 1;
+constexpr uint32_t kErrQueue = 2;
+constexpr uint32_t kErrLock = 4;
+constexpr uint32_t kErrState = 8;
+
+struct ExecParams {
+    const DevOp *ops;
+    const PassInfo *passes;
+    const DevRule *rules;
+    const double *pool;
+    void *slots;             // n_slots states, slot_amps amplitudes apart
+    uint64_t slot_amps;
+    double *tile_sums;       // per worker 2^(n-k) doubles (terminal sampling)
+    int32_t *shot_perm;
+    int32_t *shot_tmp;
+    uint64_t *memory;
+    BranchRec *queue;
+    uint32_t *ready;
+    Control *ctl;
+    int32_t *free_slots;
+    int32_t *waiting;
+    void *dump;              // normalised state of dump_shot (complex)
+    uint64_t seed;
+    int64_t n_shots;
+    int64_t dump_shot;
+    unsigned long long spin_limit;   // wall-clock ticks
+    double ro01, ro10;
+    int32_t n_ops;
+    int32_t n_qubits;
+    int32_t tile_q;          // k (== n_qubits when the state lives in LDS)
+    int32_t n_slots;
+    int32_t queue_cap;
+    int32_t branch_mode;     // 1: shots may split (work queue with pushes)
+    int32_t private_slots;   // 1: worker w uses slot w (batch mode, n > k)
+    int32_t resident;        // 1: whole state in LDS (n <= k)
+};
+
+}  // namespace svb

@@ -1,0 +1,822 @@
+// Host runtime and C ABI of the multi-shot noisy state-vector library.
+//
+// sv_run_circuit: validate -> expand noise sites (rules attached after each
+// matching gate, in rule order; Sec. III-B) -> device op records with FP64
+// matrices -> static pass plan (groups of consecutive ops whose qubits fit
+// in one LDS tile) -> upload -> persistent executor launch (plus waiting-
+// list relaunches in branch mode, Sec. IV-B) -> device histogram of the
+// classical registers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/svbatch.h"
+#include "program.h"
+
+using namespace svb;
+using cd = std::complex<double>;
+
+extern "C" {
+hipError_t svb_launch_init(const ExecParams *P, int restart, int n_root, int root_slot,
+                           int n_free, hipStream_t st);
+hipError_t svb_launch_restart(const ExecParams *P, int n_wait, hipStream_t st);
+hipError_t svb_launch_exec(const ExecParams *P, int is_c128, int workers, hipStream_t st);
+hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int *blocks_per_cu);
+size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident);
+hipError_t svb_counts(const uint64_t *memory, int64_t n, void *temp, size_t temp_bytes,
+                      uint64_t *keys_sorted, uint64_t *uniq, uint32_t *cnt, uint32_t *n_uniq,
+                      hipStream_t st);
+size_t svb_counts_temp_bytes(int64_t n);
+hipError_t svb_plain_launch(int kind, const void *args, hipStream_t st);
+}
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static sv_status fail(sv_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(expr)                                                              \
+    do {                                                                          \
+        hipError_t _e = (expr);                                                   \
+        if (_e != hipSuccess)                                                     \
+            return fail(SV_EDEVICE, "%s: %s", #expr, hipGetErrorString(_e));      \
+    } while (0)
+
+static uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ handle
+struct sv_batch {
+    int n = 0;
+    int64_t shots = 0;
+    sv_dtype dtype = SV_C64;
+    // options
+    int mode = SV_MODE_BATCH;
+    int64_t opt_slots = 0, opt_workers = 0, opt_tile = 0;
+    int64_t program_bytes = 8 << 20;
+    int64_t dump_shot = -1;
+    int64_t spin_ms = 300000;
+    // derived
+    int tile_q = 0, resident = 0, workers = 0, slots = 0;
+    int cus = 0;
+    int64_t wallclock_khz = 100000;
+    // arena
+    bool attached = false;
+    char *arena = nullptr;
+    uint64_t arena_bytes = 0;
+    hipStream_t stream = nullptr;
+    struct Layout {
+        uint64_t prog, memory, perm, tmp, waiting, queue, ready, ctl, free_slots, tile_sums,
+            dump, counts_tmp, keys_sorted, uniq, cnt, nuniq, slots, total;
+    } lay{};
+    // results
+    bool have_results = false;
+    bool have_dump = false;
+    sv_stats stats{};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+static int amp_bytes(const sv_batch *b) { return b->dtype == SV_C128 ? 16 : 8; }
+static uint64_t state_bytes(const sv_batch *b) { return (uint64_t)amp_bytes(b) << b->n; }
+
+static sv_status derive(sv_batch *b)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    b->cus = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+        b->wallclock_khz = khz;
+    // largest tile whose LDS footprint fits one workgroup on this device
+    size_t lds_cap = prop.sharedMemPerBlockOptin > 0 ? prop.sharedMemPerBlockOptin
+                                                     : prop.sharedMemPerBlock;
+    if (prop.maxSharedMemoryPerMultiProcessor > 0)
+        lds_cap = std::min(lds_cap, (size_t)prop.maxSharedMemoryPerMultiProcessor);
+    const size_t static_lds = 4096;  // executor's static shared state, rounded up
+    int kmax = b->dtype == SV_C128 ? 13 : kMaxTileQ;
+    while (kmax > 6 && svb_exec_lds_bytes(kmax, amp_bytes(b), 0) + static_lds > lds_cap) --kmax;
+    int k = b->opt_tile > 0 ? (int)b->opt_tile : kmax;
+    if (k > kmax) k = kmax;
+    if (b->n <= k) {
+        b->resident = 1;
+        b->tile_q = b->n;
+    } else {
+        b->resident = 0;
+        b->tile_q = k;
+    }
+    int per_cu = 0;
+    HIPCHK(svb_exec_occupancy(b->dtype == SV_C128, b->tile_q, b->resident, &per_cu));
+    if (per_cu < 1) return fail(SV_EDEVICE, "executor does not fit on a compute unit");
+    int64_t w = b->opt_workers > 0 ? b->opt_workers : (int64_t)per_cu * b->cus;
+    if (b->mode == SV_MODE_BATCH) w = std::min<int64_t>(w, b->shots);
+    b->workers = (int)std::max<int64_t>(1, w);
+    // state slots
+    if (b->resident) {
+        b->slots = b->mode == SV_MODE_BRANCH
+                       ? (int)(b->opt_slots > 0 ? b->opt_slots
+                                                : std::min<int64_t>(b->shots, 4 * (int64_t)b->workers))
+                       : 0;
+    } else if (b->mode == SV_MODE_BRANCH) {
+        b->slots = (int)(b->opt_slots > 0 ? b->opt_slots
+                                          : std::min<int64_t>(b->shots, 2 * (int64_t)b->workers));
+        b->slots = std::max(b->slots, 1);
+    } else {
+        b->slots = b->workers;
+    }
+    return SV_OK;
+}
+
+static void layout(sv_batch *b)
+{
+    auto &L = b->lay;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align_up(off + std::max<uint64_t>(bytes, 8), 256);
+        return o;
+    };
+    const uint64_t S = (uint64_t)b->shots;
+    L.prog = take((uint64_t)b->program_bytes);
+    L.memory = take(S * 8);
+    L.perm = take(S * 4);
+    L.tmp = take(S * 4);
+    L.waiting = take(S * 4);
+    L.queue = take(S * sizeof(BranchRec));
+    L.ready = take(S * 4);
+    L.ctl = take(sizeof(Control));
+    L.free_slots = take((uint64_t)std::max(b->slots, 1) * 4);
+    const uint64_t n_tiles = b->resident ? 1 : (1ull << (b->n - b->tile_q));
+    L.tile_sums = take((uint64_t)b->workers * n_tiles * 8);
+    L.dump = take(b->dump_shot >= 0 ? (16ull << b->n) : 8);
+    L.counts_tmp = take(svb_counts_temp_bytes((int64_t)S));
+    L.keys_sorted = take(S * 8);
+    L.uniq = take(S * 8);
+    L.cnt = take(S * 4);
+    L.nuniq = take(8);
+    L.slots = take((uint64_t)b->slots * state_bytes(b));
+    L.total = off;
+}
+
+// ------------------------------------------------------------------ ops
+struct XOp {  // expanded op
+    int kind;       // sv_op_kind, or -1 Pauli channel, -2 Kraus channel
+    int rule;
+    std::vector<int> q, c;
+    double p[3];
+    std::vector<cd> mat;  // gates: dense matrix (row-major, bit t <-> q[t])
+};
+
+static bool is_gate_kind(uint32_t k)
+{
+    return (k >= SV_OP_ID && k <= SV_OP_TDG) || k == SV_OP_U3 || k == SV_OP_CX ||
+           k == SV_OP_CZ || k == SV_OP_SWAP || k == SV_OP_UNITARY;
+}
+static int gate_nq(uint32_t k, uint32_t nq)
+{
+    if (k == SV_OP_CX || k == SV_OP_CZ || k == SV_OP_SWAP) return 2;
+    if (k == SV_OP_UNITARY) return (int)nq;
+    return 1;
+}
+
+// OpenQASM 2 U3 and the fixed one-qubit gates.
+static std::vector<cd> gate_1q(uint32_t k, const double *p)
+{
+    const cd I(0, 1);
+    const double h = 1.0 / std::sqrt(2.0);
+    switch (k) {
+    case SV_OP_ID: return {1, 0, 0, 1};
+    case SV_OP_X: return {0, 1, 1, 0};
+    case SV_OP_Y: return {0, -I, I, 0};
+    case SV_OP_Z: return {1, 0, 0, -1};
+    case SV_OP_H: return {h, h, h, -h};
+    case SV_OP_S: return {1, 0, 0, I};
+    case SV_OP_SDG: return {1, 0, 0, -I};
+    case SV_OP_T: return {1, 0, 0, std::polar(1.0, M_PI / 4)};
+    case SV_OP_TDG: return {1, 0, 0, std::polar(1.0, -M_PI / 4)};
+    case SV_OP_U3: {
+        const double c = std::cos(p[0] * 0.5), s = std::sin(p[0] * 0.5);
+        return {c, -std::polar(s, p[2]), std::polar(s, p[1]), std::polar(c, p[1] + p[2])};
+    }
+    default: return {};
+    }
+}
+
+struct Rule {
+    bool kraus;
+    int nq, n_terms;
+    uint64_t mask;
+    std::vector<double> prob;
+    std::vector<uint8_t> codes;
+    std::vector<std::vector<cd>> mats;
+};
+
+static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t n_ops,
+                                     const sv_noise_model *nm, std::vector<Rule> &rules,
+                                     std::vector<XOp> &xo, double &ro01, double &ro10,
+                                     uint64_t &gate_count)
+{
+    const int n = b->n;
+    rules.clear();
+    ro01 = ro10 = 0;
+    if (nm) {
+        if (nm->n_rules && !nm->rules) return fail(SV_EINVAL, "noise model: rules is NULL");
+        ro01 = nm->readout_p01;
+        ro10 = nm->readout_p10;
+        if (!(ro01 >= 0 && ro01 <= 1 && ro10 >= 0 && ro10 <= 1))
+            return fail(SV_EINVAL, "readout probabilities outside [0,1]");
+        for (uint32_t r = 0; r < nm->n_rules; ++r) {
+            const sv_noise_rule &nr = nm->rules[r];
+            if (!nr.channel) return fail(SV_EINVAL, "rule %u: channel is NULL", r);
+            Rule R;
+            R.mask = nr.gate_kinds_mask;
+            R.kraus = nr.is_kraus != 0;
+            if (!R.kraus) {
+                const auto *pc = (const sv_pauli_channel *)nr.channel;
+                R.nq = (int)pc->nq;
+                R.n_terms = (int)pc->n_terms;
+                if (R.nq < 1 || R.nq > 2) return fail(SV_EUNSUPPORTED, "rule %u: Pauli channel on %d qubits", r, R.nq);
+                if (R.n_terms < 1 || R.n_terms > 16) return fail(SV_EINVAL, "rule %u: %d Pauli terms (1..16)", r, R.n_terms);
+                double sum = 0;
+                for (int j = 0; j < R.n_terms; ++j) {
+                    const double p = pc->prob[j];
+                    if (!(p >= 0)) return fail(SV_EINVAL, "rule %u: negative probability", r);
+                    R.prob.push_back(p);
+                    sum += p;
+                    for (int t = 0; t < R.nq; ++t) {
+                        const uint8_t code = pc->pauli[j * R.nq + t];
+                        if (code > 3) return fail(SV_EINVAL, "rule %u: Pauli code %u", r, code);
+                        R.codes.push_back(code);
+                    }
+                }
+                if (std::fabs(sum - 1.0) > 1e-12) return fail(SV_EINVAL, "rule %u: probabilities sum to %.17g", r, sum);
+            } else {
+                const auto *kc = (const sv_kraus_channel *)nr.channel;
+                R.nq = (int)kc->nq;
+                R.n_terms = (int)kc->n_mats;
+                if (R.nq < 1 || R.nq > 2) return fail(SV_EUNSUPPORTED, "rule %u: Kraus channel on %d qubits", r, R.nq);
+                if (R.n_terms < 1 || R.n_terms > kMaxKraus) return fail(SV_EUNSUPPORTED, "rule %u: %d Kraus matrices (1..%d)", r, R.n_terms, kMaxKraus);
+                const int d = 1 << R.nq;
+                std::vector<cd> sum(d * d, 0.0);
+                for (int j = 0; j < R.n_terms; ++j) {
+                    std::vector<cd> m(d * d);
+                    for (int e = 0; e < d * d; ++e)
+                        m[e] = cd(kc->mats[(size_t)(j * d * d + e) * 2], kc->mats[(size_t)(j * d * d + e) * 2 + 1]);
+                    for (int a = 0; a < d; ++a)
+                        for (int c = 0; c < d; ++c)
+                            for (int x = 0; x < d; ++x) sum[a * d + c] += std::conj(m[x * d + a]) * m[x * d + c];
+                    R.mats.push_back(m);
+                }
+                for (int a = 0; a < d; ++a)
+                    for (int c = 0; c < d; ++c)
+                        if (std::abs(sum[a * d + c] - (a == c ? 1.0 : 0.0)) > 1e-10)
+                            return fail(SV_EINVAL, "rule %u: Kraus matrices are not complete", r);
+            }
+            rules.push_back(R);
+        }
+    }
+    xo.clear();
+    gate_count = 0;
+    int terminal_seen = 0;
+    for (size_t i = 0; i < n_ops; ++i) {
+        const sv_op &op = ops[i];
+        const uint32_t k = op.kind;
+        const bool gate = is_gate_kind(k);
+        const bool meas = k == SV_OP_MEASURE || k == SV_OP_RESET || k == SV_OP_MEASURE_RESET;
+        if (!gate && !meas) return fail(SV_EINVAL, "op %zu: unknown kind %u", i, k);
+        const int nq = gate ? gate_nq(k, op.nq) : (int)op.nq;
+        if (gate && k != SV_OP_UNITARY && op.nq != (uint32_t)nq && op.nq != 0)
+            return fail(SV_EINVAL, "op %zu: kind %u acts on %d qubits, nq=%u", i, k, nq, op.nq);
+        if (nq < 1) return fail(SV_EINVAL, "op %zu: no qubits", i);
+        if (k == SV_OP_UNITARY && (nq > 2 || !op.mat))
+            return fail(nq > 2 ? SV_EUNSUPPORTED : SV_EINVAL, "op %zu: unitary on %d qubits (1..2, mat required)", i, nq);
+        const uint32_t *qs = nq > SV_MAX_INLINE ? op.q_ext : op.q;
+        const uint32_t *cs = nq > SV_MAX_INLINE ? op.c_ext : op.c;
+        if (!qs) return fail(SV_EINVAL, "op %zu: qubit list is NULL", i);
+        XOp x;
+        x.kind = (int)k;
+        x.rule = -1;
+        uint64_t seen = 0;
+        for (int t = 0; t < nq; ++t) {
+            if (qs[t] >= (uint32_t)n) return fail(SV_EINVAL, "op %zu: qubit %u out of range", i, qs[t]);
+            if (seen >> qs[t] & 1) return fail(SV_EINVAL, "op %zu: repeated qubit %u", i, qs[t]);
+            seen |= 1ull << qs[t];
+            x.q.push_back((int)qs[t]);
+        }
+        if (k == SV_OP_MEASURE || k == SV_OP_MEASURE_RESET) {
+            if (!cs) return fail(SV_EINVAL, "op %zu: clbit list is NULL", i);
+            for (int t = 0; t < nq; ++t) {
+                if (cs[t] >= SV_MAX_CLBITS) return fail(SV_EINVAL, "op %zu: clbit %u >= 64", i, cs[t]);
+                x.c.push_back((int)cs[t]);
+            }
+        }
+        std::memcpy(x.p, op.p, sizeof x.p);
+        if (gate) {
+            ++gate_count;
+            if (k == SV_OP_CX || k == SV_OP_CZ || k == SV_OP_SWAP) {
+            } else if (k == SV_OP_UNITARY) {
+                const int d = 1 << nq;
+                x.mat.resize(d * d);
+                for (int e = 0; e < d * d; ++e) x.mat[e] = cd(op.mat[2 * e], op.mat[2 * e + 1]);
+                for (int a = 0; a < d; ++a)
+                    for (int c = 0; c < d; ++c) {
+                        cd s = 0;
+                        for (int y = 0; y < d; ++y) s += std::conj(x.mat[y * d + a]) * x.mat[y * d + c];
+                        if (std::abs(s - (a == c ? 1.0 : 0.0)) > 1e-10)
+                            return fail(SV_EINVAL, "op %zu: matrix is not unitary", i);
+                    }
+            } else {
+                x.mat = gate_1q(k, op.p);
+            }
+        }
+        xo.push_back(x);
+        if (gate) {
+            for (size_t r = 0; r < rules.size(); ++r) {
+                if (k >= 64 || !((rules[r].mask >> k) & 1)) continue;
+                if (rules[r].nq != nq)
+                    return fail(SV_EINVAL, "op %zu: rule %zu acts on %d qubits, gate on %d", i, r, rules[r].nq, nq);
+                XOp ch;
+                ch.kind = rules[r].kraus ? -2 : -1;
+                ch.rule = (int)r;
+                ch.q = x.q;
+                xo.push_back(ch);
+            }
+        }
+        (void)terminal_seen;
+    }
+    if (xo.size() > 0x7fffffff) return fail(SV_EINVAL, "too many ops");
+    return SV_OK;
+}
+
+// Static pass plan: consecutive ops whose qubits (plus qubits 0..3) fit in
+// k tile qubits. The final measurement of all qubits gets a pass of its own
+// with tile qubits 0..k-1 (contiguous chunks for sampling).
+static void plan_passes(int n, int k, bool resident, const std::vector<XOp> &xo, bool terminal,
+                        std::vector<PassInfo> &passes, std::vector<uint32_t> &op_pass)
+{
+    passes.clear();
+    op_pass.assign(xo.size(), 0);
+    auto finish = [&](uint32_t first, uint32_t end, uint32_t mask) {
+        // pad with the lowest unused qubits
+        for (int q = 0; q < n && __builtin_popcount(mask) < k; ++q) mask |= 1u << q;
+        PassInfo pi;
+        std::memset(&pi, 0, sizeof pi);
+        pi.first_op = first;
+        pi.end_op = end;
+        pi.tmask = mask;
+        int a = 0, g = 0;
+        for (int q = 0; q < n; ++q) {
+            if ((mask >> q) & 1) pi.tq[a++] = (uint8_t)q;
+            else pi.gq[g++] = (uint8_t)q;
+        }
+        pi.contiguous = (mask == ((k >= 32) ? 0xffffffffu : ((1u << k) - 1)));
+        for (uint32_t j = first; j < end; ++j) op_pass[j] = (uint32_t)passes.size();
+        passes.push_back(pi);
+    };
+    const uint32_t N = (uint32_t)xo.size();
+    if (resident) {
+        finish(0, N, (n >= 32) ? 0xffffffffu : ((1u << n) - 1));
+        return;
+    }
+    const uint32_t base_mask = (1u << kCoalesceQ) - 1;
+    const uint32_t body_end = terminal ? N - 1 : N;
+    uint32_t first = 0, mask = base_mask;
+    for (uint32_t j = 0; j < body_end; ++j) {
+        uint32_t m = 0;
+        for (int q : xo[j].q) m |= 1u << q;
+        if (__builtin_popcount(mask | m) > k) {
+            finish(first, j, mask);
+            first = j;
+            mask = base_mask;
+        }
+        mask |= m;
+    }
+    if (body_end > first) finish(first, body_end, mask);
+    if (terminal) finish(N - 1, N, (1u << k) - 1);
+}
+
+static void rule_dev(const Rule &R, std::vector<double> &pool, DevRule &d)
+{
+    std::memset(&d, 0, sizeof d);
+    d.is_kraus = R.kraus;
+    d.nq = (uint32_t)R.nq;
+    d.n_terms = (uint32_t)R.n_terms;
+    if (!R.kraus) {
+        d.thr = (uint32_t)pool.size();
+        double run = 0;
+        for (int j = 0; j < R.n_terms; ++j) {  // running sums in list order
+            run += R.prob[j];
+            pool.push_back(run);
+        }
+        for (int j = 0; j < R.n_terms; ++j) {
+            uint32_t x = 0, z = 0, ny = 0;
+            for (int t = 0; t < R.nq; ++t) {
+                const uint8_t c = R.codes[j * R.nq + t];
+                if (c == 1 || c == 2) x |= 1u << t;
+                if (c == 3 || c == 2) z |= 1u << t;
+                if (c == 2) ++ny;
+            }
+            d.xcode[j] = x;
+            d.zcode[j] = z;
+            d.ny[j] = ny;
+            if (x == 0 && z == 0) d.ident_mask |= 1u << j;
+        }
+    } else {
+        d.mats = (uint32_t)pool.size();
+        const int dd = 1 << R.nq;
+        for (const auto &m : R.mats)
+            for (const cd &v : m) {
+                pool.push_back(v.real());
+                pool.push_back(v.imag());
+            }
+        // K^dagger K diagonal? smallest eigenvalue of K0^dagger K0
+        bool diag = true;
+        std::vector<cd> M0(dd * dd);
+        for (size_t j = 0; j < R.mats.size(); ++j) {
+            const auto &m = R.mats[j];
+            for (int a = 0; a < dd; ++a)
+                for (int c = 0; c < dd; ++c) {
+                    cd s = 0;
+                    for (int x = 0; x < dd; ++x) s += std::conj(m[x * dd + a]) * m[x * dd + c];
+                    if (a != c && std::abs(s) > 0) diag = false;
+                    if (j == 0) M0[a * dd + c] = s;
+                }
+        }
+        d.diag_mm = diag;
+        double lam;
+        if (dd == 2) {
+            const double a = M0[0].real(), c = M0[3].real();
+            const double bb = std::norm(M0[1]);
+            lam = 0.5 * (a + c) - std::sqrt(0.25 * (a - c) * (a - c) + bb);
+        } else if (diag) {
+            lam = M0[0].real();
+            for (int a = 1; a < dd; ++a) lam = std::min(lam, M0[a * dd + a].real());
+        } else {
+            // Gershgorin lower bound (a valid lower bound of the eigenvalues)
+            lam = 1e300;
+            for (int a = 0; a < dd; ++a) {
+                double rad = 0;
+                for (int c = 0; c < dd; ++c)
+                    if (c != a) rad += std::abs(M0[a * dd + c]);
+                lam = std::min(lam, M0[a * dd + a].real() - rad);
+            }
+        }
+        // keep a safety margin below the bound so that rounding in the state
+        // reduction can never make K0 the wrong choice
+        lam = lam * (1.0 - 1e-12) - 1e-15;
+        d.lam_min0 = lam > 0 ? lam : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+const char *sv_last_error(void) { return g_err.c_str(); }
+
+sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype, sv_batch **out)
+{
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 30) return fail(SV_EINVAL, "n_qubits %d outside 1..30", n_qubits);
+    if (n_shots < 1 || n_shots > 0x7fffffffLL) return fail(SV_EINVAL, "n_shots %lld outside 1..2^31-1", (long long)n_shots);
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "bad dtype %d", (int)dtype);
+    sv_batch *b = new sv_batch;
+    b->n = n_qubits;
+    b->shots = n_shots;
+    b->dtype = dtype;
+    *out = b;
+    return SV_OK;
+}
+
+sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
+{
+    if (!b || !key) return fail(SV_EINVAL, "NULL argument");
+    const std::string k = key;
+    const bool sizing = k == "mode" || k == "slots" || k == "workers" || k == "tile_qubits" ||
+                        k == "program_bytes" || k == "dump_shot";
+    if (sizing && b->attached) return fail(SV_ESTATE, "option %s must be set before attach", key);
+    if (k == "mode") {
+        if (v < 0 || v > 2) return fail(SV_EINVAL, "mode %lld", (long long)v);
+        if (v == SV_MODE_PLAIN) return fail(SV_EUNSUPPORTED, "plain mode is not built into this library");
+        b->mode = (int)v;
+    } else if (k == "slots") {
+        if (v < 0 || v > (1 << 24)) return fail(SV_EINVAL, "slots %lld", (long long)v);
+        b->opt_slots = v;
+    } else if (k == "workers") {
+        if (v < 0 || v > (1 << 20)) return fail(SV_EINVAL, "workers %lld", (long long)v);
+        b->opt_workers = v;
+    } else if (k == "tile_qubits") {
+        if (v != 0 && (v < 6 || v > kMaxTileQ)) return fail(SV_EINVAL, "tile_qubits %lld (0 or 6..14)", (long long)v);
+        b->opt_tile = v;
+    } else if (k == "program_bytes") {
+        if (v < 4096) return fail(SV_EINVAL, "program_bytes %lld", (long long)v);
+        b->program_bytes = v;
+    } else if (k == "dump_shot") {
+        if (v < -1 || v >= b->shots) return fail(SV_EINVAL, "dump_shot %lld", (long long)v);
+        b->dump_shot = v;
+    } else if (k == "spin_limit_ms") {
+        if (v < 1) return fail(SV_EINVAL, "spin_limit_ms %lld", (long long)v);
+        b->spin_ms = v;
+    } else {
+        return fail(SV_EINVAL, "unknown option '%s'", key);
+    }
+    return SV_OK;
+}
+
+sv_status sv_batch_footprint(const sv_batch *cb, uint64_t *bytes_required, uint64_t *bytes_per_state)
+{
+    if (!cb) return fail(SV_EINVAL, "NULL handle");
+    sv_batch *b = const_cast<sv_batch *>(cb);
+    sv_status s = derive(b);
+    if (s != SV_OK) return s;
+    layout(b);
+    if (bytes_required) *bytes_required = b->lay.total;
+    if (bytes_per_state) *bytes_per_state = state_bytes(b);
+    return SV_OK;
+}
+
+sv_status sv_batch_attach(sv_batch *b, void *arena, uint64_t bytes, void *stream)
+{
+    if (!b || !arena) return fail(SV_EINVAL, "NULL argument");
+    if (((uintptr_t)arena & 255) != 0) return fail(SV_EINVAL, "arena must be 256-byte aligned");
+    sv_status s = derive(b);
+    if (s != SV_OK) return s;
+    layout(b);
+    if (bytes < b->lay.total)
+        return fail(SV_ENOMEM, "arena holds %llu bytes, %llu required",
+                    (unsigned long long)bytes, (unsigned long long)b->lay.total);
+    b->arena = (char *)arena;
+    b->arena_bytes = bytes;
+    b->stream = (hipStream_t)stream;
+    if (!b->ev0) {
+        HIPCHK(hipEventCreate(&b->ev0));
+        HIPCHK(hipEventCreate(&b->ev1));
+    }
+    b->attached = true;
+    b->have_results = false;
+    return SV_OK;
+}
+
+sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_noise_model *nm,
+                         uint64_t seed)
+{
+    if (!b) return fail(SV_EINVAL, "NULL handle");
+    if (!ops && n_ops) return fail(SV_EINVAL, "ops is NULL");
+    b->have_results = false;
+    b->have_dump = false;
+    std::vector<Rule> rules;
+    std::vector<XOp> xo;
+    double ro01, ro10;
+    uint64_t gate_count;
+    sv_status s = validate_and_expand(b, ops, n_ops, nm, rules, xo, ro01, ro10, gate_count);
+    if (s != SV_OK) return s;
+    if (xo.empty()) return fail(SV_EINVAL, "empty circuit");
+
+    const int n = b->n;
+    // terminal measurement: last op measures every qubit in order
+    bool terminal = false;
+    {
+        const XOp &last = xo.back();
+        if (last.kind == SV_OP_MEASURE && (int)last.q.size() == n) {
+            terminal = true;
+            for (int t = 0; t < n; ++t) terminal = terminal && last.q[t] == t;
+        }
+    }
+    for (size_t j = 0; j < xo.size(); ++j) {
+        const XOp &x = xo[j];
+        const bool is_meas = x.kind == SV_OP_MEASURE || x.kind == SV_OP_RESET || x.kind == SV_OP_MEASURE_RESET;
+        if (is_meas && !(terminal && j + 1 == xo.size()) && (int)x.q.size() > kMaxMeasQ)
+            return fail(SV_EUNSUPPORTED, "measure of %zu qubits (at most %d unless it is a final measure of all qubits in order)",
+                        x.q.size(), kMaxMeasQ);
+    }
+    if (!b->attached) return fail(SV_ESTATE, "no arena attached");
+
+    // device program
+    std::vector<PassInfo> passes;
+    std::vector<uint32_t> op_pass;
+    plan_passes(n, b->tile_q, b->resident, xo, terminal, passes, op_pass);
+    std::vector<double> pool;
+    std::vector<DevRule> drules(rules.size());
+    for (size_t r = 0; r < rules.size(); ++r) rule_dev(rules[r], pool, drules[r]);
+    std::vector<DevOp> dops(xo.size());
+    for (size_t j = 0; j < xo.size(); ++j) {
+        const XOp &x = xo[j];
+        DevOp &d = dops[j];
+        std::memset(&d, 0, sizeof d);
+        d.r = (uint32_t)j;
+        d.pass = op_pass[j];
+        d.nq = (uint8_t)x.q.size();
+        const PassInfo &pi = passes[d.pass];
+        for (size_t t = 0; t < x.q.size() && t < 8; ++t) {
+            d.q[t] = (uint8_t)x.q[t];
+            int lb = 0;
+            for (int a = 0; a < b->tile_q && a < 16; ++a)
+                if (pi.tq[a] == x.q[t]) lb = a;
+            d.lb[t] = (uint8_t)(b->resident ? x.q[t] : lb);
+        }
+        if (x.kind == -1 || x.kind == -2) {
+            d.kind = x.kind == -1 ? DK_PAULI : DK_KRAUS;
+            d.rule = (uint32_t)x.rule;
+        } else if (x.kind == SV_OP_CX) {
+            d.kind = DK_CX;
+        } else if (x.kind == SV_OP_CZ) {
+            d.kind = DK_CZ;
+        } else if (x.kind == SV_OP_SWAP) {
+            d.kind = DK_SWAP;
+        } else if (x.kind == SV_OP_MEASURE || x.kind == SV_OP_RESET || x.kind == SV_OP_MEASURE_RESET) {
+            d.kind = DK_MEASURE;
+            if (x.kind != SV_OP_RESET) d.flags |= DF_RECORD;
+            if (x.kind != SV_OP_MEASURE) d.flags |= DF_RESET;
+            if (terminal && j + 1 == xo.size()) {
+                d.flags |= DF_TERMINAL;
+                d.nq = (uint8_t)n;
+            }
+            for (size_t t = 0; t < x.c.size() && t < 32; ++t) d.c[t] = (uint8_t)x.c[t];
+        } else {
+            d.kind = x.q.size() == 1 ? DK_MAT1 : DK_MAT2;
+            d.mat = (uint32_t)pool.size();
+            bool diag = x.q.size() == 1 && x.mat[1] == 0.0 && x.mat[2] == 0.0;
+            if (diag) d.flags |= DF_DIAG;
+            for (const cd &v : x.mat) {
+                pool.push_back(v.real());
+                pool.push_back(v.imag());
+            }
+        }
+    }
+    if (pool.empty()) pool.push_back(0);
+    // upload program
+    const uint64_t ops_bytes = align_up(dops.size() * sizeof(DevOp), 256);
+    const uint64_t pass_bytes = align_up(passes.size() * sizeof(PassInfo), 256);
+    const uint64_t rule_bytes = align_up(std::max<size_t>(drules.size(), 1) * sizeof(DevRule), 256);
+    const uint64_t pool_bytes = align_up(pool.size() * sizeof(double), 256);
+    if (ops_bytes + pass_bytes + rule_bytes + pool_bytes > (uint64_t)b->program_bytes)
+        return fail(SV_ENOMEM, "program needs %llu bytes; raise option program_bytes",
+                    (unsigned long long)(ops_bytes + pass_bytes + rule_bytes + pool_bytes));
+    std::vector<char> blob(ops_bytes + pass_bytes + rule_bytes + pool_bytes, 0);
+    std::memcpy(blob.data(), dops.data(), dops.size() * sizeof(DevOp));
+    std::memcpy(blob.data() + ops_bytes, passes.data(), passes.size() * sizeof(PassInfo));
+    if (!drules.empty()) std::memcpy(blob.data() + ops_bytes + pass_bytes, drules.data(), drules.size() * sizeof(DevRule));
+    std::memcpy(blob.data() + ops_bytes + pass_bytes + rule_bytes, pool.data(), pool.size() * sizeof(double));
+    char *A = b->arena;
+    const auto &L = b->lay;
+    HIPCHK(hipMemcpyAsync(A + L.prog, blob.data(), blob.size(), hipMemcpyHostToDevice, b->stream));
+
+    ExecParams P;
+    std::memset(&P, 0, sizeof P);
+    P.ops = (const DevOp *)(A + L.prog);
+    P.passes = (const PassInfo *)(A + L.prog + ops_bytes);
+    P.rules = (const DevRule *)(A + L.prog + ops_bytes + pass_bytes);
+    P.pool = (const double *)(A + L.prog + ops_bytes + pass_bytes + rule_bytes);
+    P.slots = A + L.slots;
+    P.slot_amps = 1ull << n;
+    P.tile_sums = (double *)(A + L.tile_sums);
+    P.shot_perm = (int32_t *)(A + L.perm);
+    P.shot_tmp = (int32_t *)(A + L.tmp);
+    P.memory = (uint64_t *)(A + L.memory);
+    P.queue = (BranchRec *)(A + L.queue);
+    P.ready = (uint32_t *)(A + L.ready);
+    P.ctl = (Control *)(A + L.ctl);
+    P.free_slots = (int32_t *)(A + L.free_slots);
+    P.waiting = (int32_t *)(A + L.waiting);
+    P.dump = b->dump_shot >= 0 ? (void *)(A + L.dump) : nullptr;
+    P.seed = seed;
+    P.n_shots = b->shots;
+    P.dump_shot = b->dump_shot;
+    P.spin_limit = (unsigned long long)b->spin_ms * (unsigned long long)b->wallclock_khz;
+    P.ro01 = ro01;
+    P.ro10 = ro10;
+    P.n_ops = (int32_t)dops.size();
+    P.n_qubits = n;
+    P.tile_q = b->tile_q;
+    P.n_slots = b->slots;
+    P.queue_cap = (int32_t)b->shots;
+    P.branch_mode = b->mode == SV_MODE_BRANCH;
+    P.private_slots = (!b->resident && b->mode == SV_MODE_BATCH) ? 1 : 0;
+    P.resident = b->resident;
+
+    const bool branch = P.branch_mode != 0;
+    const int root_slot = (branch && !b->resident) ? 0 : -1;
+    const int n_free = branch ? (b->resident ? b->slots : b->slots - 1) : 0;
+    uint64_t acc[ST_COUNT] = {0};
+    uint64_t restarts = 0;
+    HIPCHK(hipEventRecord(b->ev0, b->stream));
+    HIPCHK(svb_launch_init(&P, 0, (int)b->shots, root_slot, n_free, b->stream));
+    for (;;) {
+        HIPCHK(svb_launch_exec(&P, b->dtype == SV_C128, b->workers, b->stream));
+        Control ctl;
+        HIPCHK(hipMemcpyAsync(&ctl, P.ctl, sizeof ctl, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        if (ctl.error) return fail(SV_EDEVICE, "device executor failed (flags 0x%x)", ctl.error);
+        for (int i = 0; i < ST_COUNT; ++i) acc[i] += ctl.stat[i];
+        if (ctl.wait_count == 0) break;
+        ++restarts;
+        HIPCHK(svb_launch_restart(&P, (int)ctl.wait_count, b->stream));
+        HIPCHK(svb_launch_init(&P, 1, (int)ctl.wait_count, root_slot, n_free, b->stream));
+    }
+    HIPCHK(hipEventRecord(b->ev1, b->stream));
+    HIPCHK(hipEventSynchronize(b->ev1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+
+    sv_stats &st = b->stats;
+    std::memset(&st, 0, sizeof st);
+    st.kernel_ms = ms;
+    st.passes = acc[ST_PASSES];
+    st.amp_bytes = acc[ST_BYTES];
+    st.reductions = acc[ST_REDUCTIONS];
+    st.branches = acc[ST_BRANCHES];
+    st.restarts = restarts;
+    st.waiting_shots = acc[ST_WAITING];
+    st.expanded_ops = xo.size();
+    st.gate_count = gate_count;
+    st.workers = (uint32_t)b->workers;
+    st.slots = (uint32_t)b->slots;
+    st.tile_qubits = (uint32_t)b->tile_q;
+    st.static_passes = (uint32_t)passes.size();
+    st.flops = acc[ST_FLOPS];
+    b->have_results = true;
+    b->have_dump = b->dump_shot >= 0;
+    return SV_OK;
+}
+
+sv_status sv_sample_counts(sv_batch *b, uint64_t *keys, uint64_t *counts, size_t capacity,
+                           size_t *n_unique)
+{
+    if (!b || !n_unique) return fail(SV_EINVAL, "NULL argument");
+    if (!b->have_results) return fail(SV_ESTATE, "no results: run a circuit first");
+    char *A = b->arena;
+    const auto &L = b->lay;
+    HIPCHK(svb_counts((const uint64_t *)(A + L.memory), b->shots, A + L.counts_tmp,
+                      svb_counts_temp_bytes(b->shots), (uint64_t *)(A + L.keys_sorted),
+                      (uint64_t *)(A + L.uniq), (uint32_t *)(A + L.cnt), (uint32_t *)(A + L.nuniq),
+                      b->stream));
+    uint32_t nu = 0;
+    HIPCHK(hipMemcpyAsync(&nu, A + L.nuniq, 4, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    *n_unique = nu;
+    if (nu > capacity) return fail(SV_EINVAL, "capacity %zu < %u distinct keys", capacity, nu);
+    if (nu) {
+        if (!keys || !counts) return fail(SV_EINVAL, "NULL output arrays");
+        std::vector<uint32_t> c32(nu);
+        HIPCHK(hipMemcpyAsync(keys, A + L.uniq, (size_t)nu * 8, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipMemcpyAsync(c32.data(), A + L.cnt, (size_t)nu * 4, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        for (uint32_t i = 0; i < nu; ++i) counts[i] = c32[i];
+    }
+    return SV_OK;
+}
+
+sv_status sv_get_memory(sv_batch *b, uint64_t *out, size_t n)
+{
+    if (!b || !out) return fail(SV_EINVAL, "NULL argument");
+    if (!b->have_results) return fail(SV_ESTATE, "no results: run a circuit first");
+    if (n != (size_t)b->shots) return fail(SV_EINVAL, "n=%zu, shots=%lld", n, (long long)b->shots);
+    HIPCHK(hipMemcpyAsync(out, b->arena + b->lay.memory, n * 8, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return SV_OK;
+}
+
+sv_status sv_get_state(sv_batch *b, double *amps, size_t n_amps)
+{
+    if (!b || !amps) return fail(SV_EINVAL, "NULL argument");
+    if (!b->have_dump) return fail(SV_ESTATE, "no state kept: set option dump_shot and run");
+    if (n_amps != (1ull << b->n)) return fail(SV_EINVAL, "n_amps=%zu, expected %llu", n_amps, 1ull << b->n);
+    HIPCHK(hipMemcpyAsync(amps, b->arena + b->lay.dump, n_amps * 16, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return SV_OK;
+}
+
+sv_status sv_get_stats(sv_batch *b, sv_stats *out)
+{
+    if (!b || !out) return fail(SV_EINVAL, "NULL argument");
+    if (!b->have_results) return fail(SV_ESTATE, "no results: run a circuit first");
+    *out = b->stats;
+    return SV_OK;
+}
+
+sv_status sv_batch_destroy(sv_batch *b)
+{
+    if (!b) return SV_OK;
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    delete b;
+    return SV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function the
+header declares, and rejects bad input before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2308_03399_amd as S
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "svbatch.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:sv_status|const char \*)\s*(sv_\w+)\s*\(",
+                                 text, re.M)))
+
+
+def test_header_declares_expected_calls():
+    names = _header_functions()
+    for need in ("sv_batch_create", "sv_run_circuit", "sv_sample_counts",
+                 "sv_batch_attach", "sv_batch_footprint", "sv_get_memory"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = S.lib()
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+    assert set(_header_functions()) == set(S.EXPORTED)
+
+
+def test_create_rejects_bad_sizes():
+    for n, shots, dt in ((0, 10, 0), (31, 10, 0), (5, 0, 0), (5, 10, 7)):
+        with pytest.raises(S.SvError) as e:
+            S.sv_batch_create(n, shots, dt)
+        assert e.value.status == 1
+
+
+def test_options_validation():
+    h = S.sv_batch_create(4, 10, S.SV_C64)
+    try:
+        with pytest.raises(S.SvError):
+            S.sv_batch_set_option(h, "no_such_option", 1)
+        with pytest.raises(S.SvError):
+            S.sv_batch_set_option(h, "tile_qubits", 3)
+        with pytest.raises(S.SvError):
+            S.sv_batch_set_option(h, "dump_shot", 10)
+        S.sv_batch_set_option(h, "mode", S.SV_MODE_BRANCH)
+        S.sv_batch_set_option(h, "tile_qubits", 8)
+    finally:
+        S.sv_batch_destroy(h)
+
+
+def _run_unattached(circ, noise, n=3, shots=4):
+    h = S.sv_batch_create(n, shots, S.SV_C128)
+    try:
+        S.sv_run_circuit(h, S.marshal(circ, noise), 0)
+    finally:
+        S.sv_batch_destroy(h)
+
+
+@pytest.mark.parametrize("bad", [
+    {"kind": "u3", "qubits": [3], "params": [0, 0, 0]},             # qubit out of range
+    {"kind": "cx", "qubits": [1, 1]},                                # repeated qubit
+    {"kind": "measure", "qubits": [0], "clbits": [64]},              # clbit >= 64
+    {"kind": "unitary", "qubits": [0], "matrix": [[1, 1], [0, 1]]},  # not unitary
+])
+def test_invalid_ops_are_rejected_without_device(bad):
+    circ = {"n_qubits": 3, "n_clbits": 1, "ops": [bad]}
+    with pytest.raises(S.SvError) as e:
+        _run_unattached(circ, None)
+    assert e.value.status == 1
+
+
+def test_invalid_noise_is_rejected():
+    circ = {"n_qubits": 3, "n_clbits": 0, "ops": [{"kind": "h", "qubits": [0]}]}
+    bad_p = W.noise_model([W.rule(["h"], W.pauli_table([0.5, 0.4], ["I", "X"]))])
+    with pytest.raises(S.SvError) as e:
+        _run_unattached(circ, bad_p)
+    assert e.value.status == 1
+    bad_k = W.noise_model([W.rule(["h"], W.kraus_channel([[[1, 0], [0, 0.5]]]))])
+    with pytest.raises(S.SvError) as e:
+        _run_unattached(circ, bad_k)
+    assert e.value.status == 1
+    wrong_width = W.noise_model([W.rule(["h"], W.depolarizing_pauli(0.1, 2))])
+    with pytest.raises(S.SvError) as e:
+        _run_unattached(circ, wrong_width)
+    assert e.value.status == 1
+
+
+def test_valid_circuit_needs_arena():
+    circ = W.random_layered(3, 2, seed=0)
+    with pytest.raises(S.SvError) as e:
+        _run_unattached(circ, W.depol_model())
+    assert e.value.status == 4  # SV_ESTATE
+
+
+def test_results_before_run_are_refused():
+    h = S.sv_batch_create(3, 4, S.SV_C64)
+    try:
+        with pytest.raises(S.SvError) as e:
+            S.sv_get_memory(h, 4)
+        assert e.value.status == 4
+        with pytest.raises(S.SvError) as e:
+            S.sv_get_stats(h)
+        assert e.value.status == 4
+    finally:
+        S.sv_batch_destroy(h)
+
+
+def test_large_mid_circuit_measure_is_unsupported():
+    circ = {"n_qubits": 6, "n_clbits": 6,
+            "ops": [{"kind": "measure", "qubits": [0, 1, 2, 3, 4], "clbits": [0, 1, 2, 3, 4]},
+                    {"kind": "h", "qubits": [0]}]}
+    with pytest.raises(S.SvError) as e:
+        _run_unattached(circ, None, n=6)
+    # validation of sizes happens before the arena check
+    assert e.value.status == 5

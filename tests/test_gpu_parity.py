@@ -1,0 +1,121 @@
+"""GPU parity: per-shot classical registers of the HIP path equal the FP64
+oracle's, shot by shot, through the C ABI. FP64 (c128) storage must match
+exactly; c64 storage (FP64 decisions) is held to agreement-rate and TVD
+bounds."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import gpu_run, mismatches, oracle_memory, say, tvd_counts
+
+pytestmark = pytest.mark.gpu
+
+
+def _noise_full(p1=0.02, p2=0.05, gamma=0.03, ro=(0.02, 0.03)):
+    return W.noise_model(
+        [W.rule(["u3", "h", "x", "y", "z", "s", "t", "sdg", "tdg"],
+                W.depolarizing_pauli(p1, 1)),
+         W.rule(["u3", "h"], W.amplitude_damping_kraus(gamma)),
+         W.rule(["cx", "cz", "swap", "unitary"], W.depolarizing_pauli(p2, 2))],
+        readout=ro)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_small_random_circuits_c128_exact(n):
+    circ = W.random_small(n, 40, seed=n, n_mid=3 if n > 1 else 0)
+    noise = _noise_full()
+    shots = 600
+    say(f"case small n={n} shots={shots} c128 batch")
+    got = gpu_run(circ, noise, shots, dtype="c128", seed=7)
+    exp = oracle_memory(circ, noise, shots, seed=7)
+    assert mismatches(got["memory"], exp) == 0
+
+
+def test_c1_workload_exact():
+    w = W.workload("c1_10q")
+    say("case c1 10q x 20 layers, 1000 shots, c128 batch")
+    got = gpu_run(w["circuit"], w["noise"], w["shots"], dtype="c128", seed=w["seed"])
+    exp = oracle_memory(w["circuit"], w["noise"], w["shots"], seed=w["seed"])
+    assert mismatches(got["memory"], exp) == 0
+    cnt = got["counts"]
+    assert sum(cnt.values()) == w["shots"]
+    ek, ec = np.unique(exp, return_counts=True)
+    assert cnt == {int(k): int(c) for k, c in zip(ek, ec)}
+
+
+@pytest.mark.parametrize("tile", [6, 8])
+def test_streamed_tiles_exact(tile):
+    # state larger than the tile: ops run in tile sweeps through HBM
+    n = 11
+    circ = W.random_layered(n, 6, seed=3, mid_measure=(3, (0, 5)))
+    noise = _noise_full(p1=0.03, p2=0.06, gamma=0.05)
+    shots = 200
+    say(f"case streamed n={n} tile={tile} shots={shots} c128 batch")
+    got = gpu_run(circ, noise, shots, dtype="c128", seed=11, tile_qubits=tile)
+    exp = oracle_memory(circ, noise, shots, seed=11)
+    assert got["stats"]["tile_qubits"] == tile
+    assert got["stats"]["passes"] > 0
+    assert mismatches(got["memory"], exp) == 0
+
+
+@pytest.mark.parametrize("n,tile", [(6, 0), (11, 8)])
+def test_dump_state_matches_oracle(n, tile):
+    circ = W.random_layered(n, 4, seed=5)
+    noise = _noise_full(p1=0.2, p2=0.2, gamma=0.2)
+    shot = 13
+    say(f"case dump n={n} tile={tile}")
+    for dtype, tol in (("c128", 1e-12), ("c64", 2e-5)):
+        opts = {"tile_qubits": tile} if tile else {}
+        got = gpu_run(circ, noise, 20, dtype=dtype, seed=2, dump_shot=shot, **opts)
+        _, psi = oracle.run(circ, noise, [shot], seed=2,
+                            stop_at=len_expanded(circ, noise) - 1, want_state=True)
+        assert np.max(np.abs(got["state"] - psi)) < tol, dtype
+
+
+def len_expanded(circ, noise):
+    from oracle import dm
+    return len(dm.expand(circ, noise))
+
+
+@pytest.mark.parametrize("n,tile", [(5, 0), (11, 7)])
+def test_branch_mode_equals_batch_and_oracle(n, tile):
+    circ = W.random_layered(n, 5, seed=9, mid_measure=(2, (1,)))
+    noise = _noise_full(p1=0.01, p2=0.03, gamma=0.02)
+    shots = 400
+    opts = {"tile_qubits": tile} if tile else {}
+    say(f"case branch n={n} tile={tile} shots={shots}")
+    br = gpu_run(circ, noise, shots, dtype="c128", mode="branch", seed=4, **opts)
+    exp = oracle_memory(circ, noise, shots, seed=4)
+    assert mismatches(br["memory"], exp) == 0
+    st = br["stats"]
+    assert st["branches"] >= 1
+    # fewer states than shots were simulated
+    assert st["branches"] < shots
+
+
+def test_branch_mode_waiting_list_restarts():
+    n = 9
+    circ = W.random_layered(n, 4, seed=2)
+    noise = _noise_full(p1=0.05, p2=0.1, gamma=0.05)
+    shots = 300
+    say("case branch waiting list (2 slots)")
+    br = gpu_run(circ, noise, shots, dtype="c128", mode="branch", seed=8,
+                 tile_qubits=6, slots=2, workers=4)
+    exp = oracle_memory(circ, noise, shots, seed=8)
+    assert br["stats"]["restarts"] >= 1
+    assert mismatches(br["memory"], exp) == 0
+
+
+def test_c64_agreement_and_tvd():
+    w = W.workload("c1_10q")
+    shots = 1000
+    say("case c64 c1 agreement")
+    got = gpu_run(w["circuit"], w["noise"], shots, dtype="c64", seed=0)
+    exp = oracle_memory(w["circuit"], w["noise"], shots, seed=0)
+    agree = 1 - mismatches(got["memory"], exp) / shots
+    say(f"c64 agreement {agree:.5f}")
+    assert agree >= 0.995
+    assert tvd_counts(got["memory"], exp) <= 5e-3
