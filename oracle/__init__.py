@@ -29,7 +29,7 @@ KIND = {"id": 0, "x": 1, "y": 2, "z": 3, "h": 4, "s": 5, "sdg": 6, "t": 7,
         "tdg": 8, "u3": 9, "cx": 16, "cz": 17, "swap": 18, "unitary": 24,
         "measure": 32, "reset": 33, "measure_reset": 34}
 PAULI_CODE = {"I": 0, "X": 1, "Y": 2, "Z": 3}
-MAXQ = 8
+MAXQ = 32
 
 
 def build(force: bool = True) -> str:

@@ -56,7 +56,8 @@ enum {
     O_PAULI_CH = 48, O_KRAUS_CH
 };
 
-#define MAXQ 8
+#define MAXQ 32   /* qubits (and clbits) per op */
+#define MAXDENSE 5 /* qubits of a dense matrix */
 
 typedef struct {
     int kind;
@@ -164,8 +165,9 @@ static void apply_dense(cplx *psi, int n, int k, const int *qs, const cplx *m)
 {
     uint64_t dim = 1ull << n, sub = 1ull << k, mask = 0;
     for (int t = 0; t < k; ++t) mask |= 1ull << qs[t];
-    cplx in[1 << MAXQ], out[1 << MAXQ];
-    uint64_t idx[1 << MAXQ];
+    cplx in[1 << MAXDENSE], out[1 << MAXDENSE];
+    uint64_t idx[1 << MAXDENSE];
+    if (k > MAXDENSE) abort();
     for (uint64_t base = 0; base < dim; ++base) {
         if (base & mask) continue;
         for (uint64_t a = 0; a < sub; ++a) {
@@ -447,7 +449,9 @@ int oracle_run(int n, int n_ops, const int *kind, const int *nq,
     for (int i = 0; i < n_ops; ++i) {
         ops[i].kind = kind[i];
         ops[i].nq = nq[i];
-        if (nq[i] < 0 || nq[i] > MAXQ) { free(ops); free(rules); return -1; }
+        if (nq[i] < 0 || nq[i] > MAXQ || (kind[i] == O_UNITARY && nq[i] > MAXDENSE)) {
+            free(ops); free(rules); return -1;
+        }
         for (int t = 0; t < MAXQ; ++t) {
             ops[i].q[t] = q[i * MAXQ + t];
             ops[i].c[t] = c[i * MAXQ + t];
@@ -459,6 +463,7 @@ int oracle_run(int n, int n_ops, const int *kind, const int *nq,
         ops[i].rule = -1;
     }
     for (int r = 0; r < n_rules; ++r) {
+        if (rnq[r] < 1 || rnq[r] > MAXDENSE) { free(ops); free(rules); return -1; }
         rules[r].gate_mask_lo = gate_mask[r];
         rules[r].type = rtype[r];
         rules[r].nq = rnq[r];
