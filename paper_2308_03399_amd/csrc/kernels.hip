@@ -30,9 +30,20 @@
 
 namespace svb {
 
+// Amplitudes and 16-byte chunks as clang vector types (usable through
+// address-space-qualified pointers, unlike the HIP vector classes).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <class R> struct V2;
-template <> struct V2<float> { using T = float2; };
-template <> struct V2<double> { using T = double2; };
+template <> struct V2<float> { using T = f32x2; };
+template <> struct V2<double> { using T = f64x2; };
+
+// LDS (address space 3) and global (address space 1) pointers, so that tile
+// accesses compile to ds_* and global_* instructions rather than flat ones.
+template <class T> using lds = __attribute__((address_space(3))) T;
+template <class T> using gbl = __attribute__((address_space(1))) T;
 
 // ------------------------------------------------------------------ RNG
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -172,21 +183,68 @@ struct WgShared {
     double wred[kMaxRed][kWG / 64];
     double tsum_n;
     int term_tile;
+    int n_ug;
+    uint64_t pass_flops;
     unsigned long long st[ST_COUNT];
 };
+
+// Register micro-op built at plan time (fused 2x2 matrices, permutations).
+enum UKind : uint8_t { UK_MAT1 = 1, UK_DIAG1 = 2, UK_CX = 3, UK_CZ = 4, UK_SWAP = 5 };
+struct UOp {
+    uint8_t kind, j0, j1, pad;
+    uint16_t mat, pad2;
+};
+struct UGroup {
+    int32_t gidx;       // static group
+    int32_t a, b;       // register group: first uop, count; LDS group: op range
+    int32_t fallback;
+};
+
+__device__ __forceinline__ void put_uop(lds<UOp> *p, const UOp &u)
+{
+    p->kind = u.kind;
+    p->j0 = u.j0;
+    p->j1 = u.j1;
+    p->pad = 0;
+    p->mat = u.mat;
+    p->pad2 = 0;
+}
+
+__device__ __forceinline__ UOp get_uop(const lds<UOp> *p)
+{
+    UOp u;
+    u.kind = p->kind;
+    u.j0 = p->j0;
+    u.j1 = p->j1;
+    u.pad = 0;
+    u.mat = p->mat;
+    u.pad2 = 0;
+    return u;
+}
 
 template <class R>
 struct Ctx {
     using A = typename V2<R>::T;
     const ExecParams &P;
-    WgShared &S;
-    A *L;              // LDS tile (2^k amplitudes)
-    uint32_t *hi_off;  // LDS: global offset of local index bits >= 4
-    int *dec;          // LDS: decided outcome of each op of the pass
-    int *cnt;          // LDS: 16 x kWG outcome counters (splits)
+    lds<WgShared> &S;
+    lds<A> *L;         // LDS tile (2^k amplitudes, swizzled positions)
+    lds<uint32_t> *hi_off;  // LDS: global offset of local index bits >= 4
+    lds<int> *dec;     // LDS: decided outcome of each op of the pass
+    lds<int> *cnt;     // LDS: 16 x kWG outcome counters (splits), aliases the uop area
+    lds<UGroup> *ug;   // LDS: register groups of the pass
+    lds<UOp> *uops;    // LDS: micro-ops of the pass
+    lds<R> *mats;      // LDS: fused matrices of the pass (8 reals each)
+    lds<double> *pend; // LDS: pending FP64 2x2 matrices during fusion (8 x 8)
     uint32_t tsize;    // 2^k
     uint32_t n_tiles;  // 2^(n-k), 1 if resident
+    uint32_t swm;      // swizzle mask of the current pass (0: identity)
+    int k;
     int tid;
+    // LDS position of tile index i: low six bits mixed with bits 6..17
+    __device__ __forceinline__ uint32_t at(uint32_t i) const
+    {
+        return i ^ (((i >> 6) ^ (i >> 12)) & swm);
+    }
 };
 
 // ----------------------------------------------------------- op sweeps
@@ -194,24 +252,24 @@ template <class R>
 __device__ void sweep_mat1(Ctx<R> &c, uint32_t b, const Mat2<R> &m, bool diag)
 {
     using A = typename V2<R>::T;
-    A *L = c.L;
+    lds<A> *L = c.L;
     if (diag) {
         for (uint32_t i = c.tid; i < c.tsize; i += kWG) {
-            const A v = L[i];
-            L[i] = ((i >> b) & 1u) ? cmul<A, R>(m.r[3], m.i[3], v)
+            const A v = L[c.at(i)];
+            L[c.at(i)] = ((i >> b) & 1u) ? cmul<A, R>(m.r[3], m.i[3], v)
                                    : cmul<A, R>(m.r[0], m.i[0], v);
         }
     } else {
         const uint32_t half = c.tsize >> 1, bit = 1u << b;
         for (uint32_t p = c.tid; p < half; p += kWG) {
             const uint32_t i0 = ins0(p, b), i1 = i0 | bit;
-            const A a = L[i0], d = L[i1];
+            const A a = L[c.at(i0)], d = L[c.at(i1)];
             A o0 = cmul<A, R>(m.r[0], m.i[0], a);
             o0 = cmac<A, R>(o0, m.r[1], m.i[1], d);
             A o1 = cmul<A, R>(m.r[2], m.i[2], a);
             o1 = cmac<A, R>(o1, m.r[3], m.i[3], d);
-            L[i0] = o0;
-            L[i1] = o1;
+            L[c.at(i0)] = o0;
+            L[c.at(i1)] = o1;
         }
     }
     __syncthreads();
@@ -232,13 +290,13 @@ __device__ void sweep_mat2(Ctx<R> &c, uint32_t b0, uint32_t b1, const double *m,
     const uint32_t lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
     const uint32_t quarter = c.tsize >> 2;
     const uint32_t m0 = 1u << b0, m1 = 1u << b1;
-    A *L = c.L;
+    lds<A> *L = c.L;
     for (uint32_t p = c.tid; p < quarter; p += kWG) {
         const uint32_t base = ins0(ins0(p, lo), hi);
         const uint32_t idx[4] = {base, base | m0, base | m1, base | m0 | m1};
         A v[4], o[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) v[a] = L[idx[a]];
+        for (int a = 0; a < 4; ++a) v[a] = L[c.at(idx[a])];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             A acc = cmul<A, R>(mr[4 * a], mi[4 * a], v[0]);
@@ -248,7 +306,7 @@ __device__ void sweep_mat2(Ctx<R> &c, uint32_t b0, uint32_t b1, const double *m,
             o[a] = acc;
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a) L[idx[a]] = o[a];
+        for (int a = 0; a < 4; ++a) L[c.at(idx[a])] = o[a];
     }
     __syncthreads();
 }
@@ -259,13 +317,13 @@ __device__ void sweep_cx(Ctx<R> &c, uint32_t bc, uint32_t bt)
     using A = typename V2<R>::T;
     const uint32_t lo = bc < bt ? bc : bt, hi = bc < bt ? bt : bc;
     const uint32_t quarter = c.tsize >> 2;
-    A *L = c.L;
+    lds<A> *L = c.L;
     for (uint32_t p = c.tid; p < quarter; p += kWG) {
         const uint32_t i = ins0(ins0(p, lo), hi) | (1u << bc);
         const uint32_t j = i | (1u << bt);
-        const A a = L[i];
-        L[i] = L[j];
-        L[j] = a;
+        const A a = L[c.at(i)];
+        L[c.at(i)] = L[c.at(j)];
+        L[c.at(j)] = a;
     }
     __syncthreads();
 }
@@ -276,13 +334,13 @@ __device__ void sweep_cz(Ctx<R> &c, uint32_t ba, uint32_t bb)
     using A = typename V2<R>::T;
     const uint32_t lo = ba < bb ? ba : bb, hi = ba < bb ? bb : ba;
     const uint32_t quarter = c.tsize >> 2;
-    A *L = c.L;
+    lds<A> *L = c.L;
     for (uint32_t p = c.tid; p < quarter; p += kWG) {
         const uint32_t i = ins0(ins0(p, lo), hi) | (1u << ba) | (1u << bb);
-        A a = L[i];
+        A a = L[c.at(i)];
         a.x = -a.x;
         a.y = -a.y;
-        L[i] = a;
+        L[c.at(i)] = a;
     }
     __syncthreads();
 }
@@ -293,13 +351,13 @@ __device__ void sweep_swap(Ctx<R> &c, uint32_t ba, uint32_t bb)
     using A = typename V2<R>::T;
     const uint32_t lo = ba < bb ? ba : bb, hi = ba < bb ? bb : ba;
     const uint32_t quarter = c.tsize >> 2;
-    A *L = c.L;
+    lds<A> *L = c.L;
     for (uint32_t p = c.tid; p < quarter; p += kWG) {
         const uint32_t base = ins0(ins0(p, lo), hi);
         const uint32_t i = base | (1u << ba), j = base | (1u << bb);
-        const A a = L[i];
-        L[i] = L[j];
-        L[j] = a;
+        const A a = L[c.at(i)];
+        L[c.at(i)] = L[c.at(j)];
+        L[c.at(j)] = a;
     }
     __syncthreads();
 }
@@ -311,18 +369,18 @@ template <class R>
 __device__ void sweep_pauli(Ctx<R> &c, uint32_t xl, uint32_t zl, uint32_t ny)
 {
     using A = typename V2<R>::T;
-    A *L = c.L;
+    lds<A> *L = c.L;
     if (xl == 0) {
         for (uint32_t i = c.tid; i < c.tsize; i += kWG)
-            L[i] = phase_ny(neg_if(L[i], __popc(i & zl)), ny);
+            L[c.at(i)] = phase_ny(neg_if(L[c.at(i)], __popc(i & zl)), ny);
     } else {
         const uint32_t xb = 31u - __clz(xl);
         const uint32_t half = c.tsize >> 1;
         for (uint32_t p = c.tid; p < half; p += kWG) {
             const uint32_t i0 = ins0(p, xb), i1 = i0 ^ xl;
-            const A a = L[i0], d = L[i1];
-            L[i0] = phase_ny(neg_if(d, __popc(i0 & zl)), ny);
-            L[i1] = phase_ny(neg_if(a, __popc(i1 & zl)), ny);
+            const A a = L[c.at(i0)], d = L[c.at(i1)];
+            L[c.at(i0)] = phase_ny(neg_if(d, __popc(i0 & zl)), ny);
+            L[c.at(i1)] = phase_ny(neg_if(a, __popc(i1 & zl)), ny);
         }
     }
     __syncthreads();
@@ -334,12 +392,12 @@ template <class R>
 __device__ void sweep_measure(Ctx<R> &c, const DevOp &op, uint32_t o, double s)
 {
     using A = typename V2<R>::T;
-    A *L = c.L;
+    lds<A> *L = c.L;
     const R sc = (R)s;
     for (uint32_t i = c.tid; i < c.tsize; i += kWG) {
         uint32_t pat = 0;
         for (int t = 0; t < op.nq; ++t) pat |= ((i >> op.lb[t]) & 1u) << t;
-        A v = L[i];
+        A v = L[c.at(i)];
         if (pat == o) {
             v.x *= sc;
             v.y *= sc;
@@ -347,7 +405,7 @@ __device__ void sweep_measure(Ctx<R> &c, const DevOp &op, uint32_t o, double s)
             v.x = 0;
             v.y = 0;
         }
-        L[i] = v;
+        L[c.at(i)] = v;
     }
     __syncthreads();
     if (op.flags & DF_RESET) {
@@ -356,9 +414,9 @@ __device__ void sweep_measure(Ctx<R> &c, const DevOp &op, uint32_t o, double s)
             const uint32_t b = op.lb[t], half = c.tsize >> 1;
             for (uint32_t p = c.tid; p < half; p += kWG) {
                 const uint32_t i0 = ins0(p, b), i1 = i0 | (1u << b);
-                const A a = L[i0];
-                L[i0] = L[i1];
-                L[i1] = a;
+                const A a = L[c.at(i0)];
+                L[c.at(i0)] = L[c.at(i1)];
+                L[c.at(i1)] = a;
             }
             __syncthreads();
         }
@@ -369,7 +427,7 @@ __device__ __forceinline__ uint64_t flops_mat1(bool diag) { return diag ? 6 : 14
 
 // Apply op j with decided outcome d (and renormalisation s) to the tile.
 template <class R>
-__device__ void apply_op(Ctx<R> &c, const DevOp &op, int d, double s)
+__device__ __noinline__ void apply_op(Ctx<R> &c, const DevOp &op, int d, double s)
 {
     const ExecParams &P = c.P;
     switch (op.kind) {
@@ -426,15 +484,310 @@ __device__ __forceinline__ uint64_t op_flops(const ExecParams &P, const DevOp &o
     }
 }
 
+
+// ----------------------------------------------------------- register groups
+// In-register ops on a thread's NR amplitudes; J, C, T are register bits.
+template <int J, class A, class R, int NR>
+__device__ __forceinline__ void r_mat1(A (&v)[NR], const R (&m)[8])
+{
+    if constexpr ((1 << J) < NR) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (i & (1 << J)) continue;
+            const int i1 = i | (1 << J);
+            const A a = v[i], b = v[i1];
+            A o0 = cmul<A, R>(m[0], m[1], a);
+            o0 = cmac<A, R>(o0, m[2], m[3], b);
+            A o1 = cmul<A, R>(m[4], m[5], a);
+            o1 = cmac<A, R>(o1, m[6], m[7], b);
+            v[i] = o0;
+            v[i1] = o1;
+        }
+    }
+}
+
+template <int J, class A, class R, int NR>
+__device__ __forceinline__ void r_diag1(A (&v)[NR], const R (&m)[8])
+{
+    if constexpr ((1 << J) < NR) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+            v[i] = (i & (1 << J)) ? cmul<A, R>(m[6], m[7], v[i]) : cmul<A, R>(m[0], m[1], v[i]);
+    }
+}
+
+template <int C, int T, class A, int NR>
+__device__ __forceinline__ void r_cx(A (&v)[NR])
+{
+    if constexpr ((1 << C) < NR && (1 << T) < NR && C != T) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (!(i & (1 << C)) || (i & (1 << T))) continue;
+            const A a = v[i];
+            v[i] = v[i | (1 << T)];
+            v[i | (1 << T)] = a;
+        }
+    }
+}
+
+template <int C, int T, class A, int NR>
+__device__ __forceinline__ void r_cz(A (&v)[NR])
+{
+    if constexpr ((1 << C) < NR && (1 << T) < NR && C != T) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if ((i & (1 << C)) && (i & (1 << T))) {
+                v[i].x = -v[i].x;
+                v[i].y = -v[i].y;
+            }
+        }
+    }
+}
+
+template <int C, int T, class A, int NR>
+__device__ __forceinline__ void r_swap(A (&v)[NR])
+{
+    if constexpr ((1 << C) < NR && (1 << T) < NR && C != T) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (!(i & (1 << C)) || (i & (1 << T))) continue;
+            const int i2 = (i ^ (1 << C)) | (1 << T);
+            const A a = v[i];
+            v[i] = v[i2];
+            v[i2] = a;
+        }
+    }
+}
+
+template <class A, class R, int NR>
+__device__ __forceinline__ void d_mat1(A (&v)[NR], int j, const R (&m)[8], bool diag)
+{
+#define SVB_M1(J)                                   \
+    case J:                                         \
+        if (diag) r_diag1<J, A, R, NR>(v, m);       \
+        else r_mat1<J, A, R, NR>(v, m);             \
+        break;
+    switch (j) { SVB_M1(0) SVB_M1(1) SVB_M1(2) SVB_M1(3) SVB_M1(4) SVB_M1(5) default: break; }
+#undef SVB_M1
+}
+
+template <class A, int NR>
+__device__ __forceinline__ void d_two(A (&v)[NR], int kind, int c, int t)
+{
+#define SVB_P(C, T)                                        \
+    case C * 8 + T:                                        \
+        if (kind == UK_CX) r_cx<C, T, A, NR>(v);           \
+        else if (kind == UK_CZ) r_cz<C, T, A, NR>(v);      \
+        else r_swap<C, T, A, NR>(v);                       \
+        break;
+#define SVB_ROW(C) SVB_P(C, 0) SVB_P(C, 1) SVB_P(C, 2) SVB_P(C, 3) SVB_P(C, 4) SVB_P(C, 5)
+    switch (c * 8 + t) { SVB_ROW(0) SVB_ROW(1) SVB_ROW(2) SVB_ROW(3) SVB_ROW(4) SVB_ROW(5) default: break; }
+#undef SVB_ROW
+#undef SVB_P
+}
+
+// Gather the thread's NR amplitudes of group gi from LDS, run the group's
+// micro-ops in registers, scatter back.
+template <class R, int NR>
+__device__ void run_group(Ctx<R> &c, const GroupInfo &gi, int first, int count)
+{
+    using A = typename V2<R>::T;
+    constexpr int RB = NR == 64 ? 6 : NR == 32 ? 5 : NR == 16 ? 4 : 3;
+    uint32_t base = 0;
+    for (int i = 0; i < c.k - RB; ++i) base |= ((uint32_t)(c.tid >> i) & 1u) << gi.cpos[i];
+    const uint32_t pb = c.at(base);
+    uint32_t pe[RB];
+#pragma unroll
+    for (int j = 0; j < RB; ++j) pe[j] = c.at(1u << gi.gpos[j]);
+    A v[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        uint32_t p = pb;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+            if ((i >> j) & 1) p ^= pe[j];
+        v[i] = c.L[p];
+    }
+    for (int q = 0; q < count; ++q) {
+        const UOp u = get_uop(c.uops + first + q);
+        if (u.kind == UK_MAT1 || u.kind == UK_DIAG1) {
+            R m[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) m[e] = c.mats[u.mat * 8 + e];
+            d_mat1<A, R, NR>(v, u.j0, m, u.kind == UK_DIAG1);
+        } else {
+            d_two<A, NR>(v, u.kind, u.j0, u.j1);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        uint32_t p = pb;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+            if ((i >> j) & 1) p ^= pe[j];
+        c.L[p] = v[i];
+    }
+    __syncthreads();
+}
+
+// ---- plan-time fusion (thread 0): per register bit a pending FP64 2x2
+// matrix collects consecutive one-qubit factors (gate, drawn Pauli, chosen
+// Kraus matrix); two-qubit permutations flush the pending factors of their
+// bits and are emitted as they are.
+__device__ __forceinline__ void m2_mul_left(lds<double> *pm, const double *a)
+{
+    // pm <- a * pm (row-major 2x2, interleaved re/im)
+    double o[8];
+    for (int r = 0; r < 2; ++r)
+        for (int cc = 0; cc < 2; ++cc) {
+            double re = 0, im = 0;
+            for (int t = 0; t < 2; ++t) {
+                const double ar = a[2 * (2 * r + t)], ai = a[2 * (2 * r + t) + 1];
+                const double br = pm[2 * (2 * t + cc)], bi = pm[2 * (2 * t + cc) + 1];
+                re += ar * br - ai * bi;
+                im += ar * bi + ai * br;
+            }
+            o[2 * (2 * r + cc)] = re;
+            o[2 * (2 * r + cc) + 1] = im;
+        }
+    for (int e = 0; e < 8; ++e) pm[e] = o[e];
+}
+
+template <class R>
+__device__ bool fuse_flush(Ctx<R> &c, int j, uint32_t &pend_set, int &nu, int &nm,
+                           uint64_t &flops)
+{
+    if (!((pend_set >> j) & 1u)) return true;
+    pend_set &= ~(1u << j);
+    const lds<double> *pm = c.pend + 8 * j;
+    const bool diag = pm[2] == 0.0 && pm[3] == 0.0 && pm[4] == 0.0 && pm[5] == 0.0;
+    for (int e = 0; e < 8; ++e) c.mats[nm * 8 + e] = (R)pm[e];
+    UOp u;
+    u.kind = diag ? UK_DIAG1 : UK_MAT1;
+    u.j0 = (uint8_t)j;
+    u.j1 = 0;
+    u.pad = 0;
+    u.mat = (uint16_t)nm;
+    u.pad2 = 0;
+    put_uop(c.uops + nu++, u);
+    ++nm;
+    flops += diag ? 6 : 14;
+    return true;
+}
+
+template <class R>
+__device__ void fuse_factor(Ctx<R> &c, int j, const double *m, double scale, uint32_t &pend_set)
+{
+    double a[8];
+    for (int e = 0; e < 8; ++e) a[e] = m[e] * scale;
+    lds<double> *pm = c.pend + 8 * j;
+    if ((pend_set >> j) & 1u) {
+        m2_mul_left(pm, a);
+    } else {
+        for (int e = 0; e < 8; ++e) pm[e] = a[e];
+        pend_set |= 1u << j;
+    }
+}
+
+// Build the register groups and micro-ops of [S.start, S.end) with the
+// pass's decisions; may shorten the pass if LDS capacity runs out.
+template <class R>
+__device__ __noinline__ void build_uops(Ctx<R> &c)
+{
+    const ExecParams &P = c.P;
+    lds<WgShared> &S = c.S;
+    int ng = 0, nu = 0, nm = 0;
+    uint64_t flops = 0;
+    int j = S.start;
+    bool cut = false;
+    while (j < S.end && !cut) {
+        const uint32_t g = P.ops[j].group;
+        const GroupInfo &gi = P.groups[g];
+        const int a = j, b = min((int)gi.end_op, S.end);
+        if (ng >= kMaxPassGroups) { cut = true; S.end = j; break; }
+        if (gi.fallback) {
+            c.ug[ng].gidx = (int)g;
+            c.ug[ng].a = a;
+            c.ug[ng].b = b;
+            c.ug[ng].fallback = 1;
+            for (int o = a; o < b; ++o) flops += op_flops(P, P.ops[o], c.dec[o - S.start]);
+            ++ng;
+            j = b;
+            continue;
+        }
+        const int first = nu;
+        uint32_t pend_set = 0;
+        int o = a;
+        for (; o < b; ++o) {
+            // room for this op (<= 3 micro-ops) and the group's final flush (<= 8)
+            if (nu + 11 > kMaxPassUops || nm + 11 > kMaxPassMats) { cut = true; break; }
+            const DevOp &op = P.ops[o];
+            const int d = c.dec[o - S.start];
+            const double sc = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
+            switch (op.kind) {
+            case DK_MAT1:
+                fuse_factor(c, op.rb[0], P.pool + op.mat, 1.0, pend_set);
+                break;
+            case DK_KRAUS: {
+                const DevRule &ru = P.rules[op.rule];
+                fuse_factor(c, op.rb[0], P.pool + ru.mats + (size_t)d * 8, sc, pend_set);
+                break;
+            }
+            case DK_PAULI: {
+                const DevRule &ru = P.rules[op.rule];
+                if ((ru.ident_mask >> d) & 1u) break;
+                for (int t = 0; t < op.nq; ++t) {
+                    const uint32_t x = (ru.xcode[d] >> t) & 1u, z = (ru.zcode[d] >> t) & 1u;
+                    if (!x && !z) continue;
+                    // X = [[0,1],[1,0]], Z = [[1,0],[0,-1]], Y = [[0,-i],[i,0]]
+                    double pm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    if (x && !z) { pm[2] = 1; pm[4] = 1; }
+                    else if (!x && z) { pm[0] = 1; pm[6] = -1; }
+                    else { pm[3] = -1; pm[5] = 1; }
+                    fuse_factor(c, op.rb[t], pm, 1.0, pend_set);
+                }
+                break;
+            }
+            default: {  // CX, CZ, SWAP
+                fuse_flush(c, op.rb[0], pend_set, nu, nm, flops);
+                fuse_flush(c, op.rb[1], pend_set, nu, nm, flops);
+                UOp u;
+                u.kind = op.kind == DK_CX ? UK_CX : op.kind == DK_CZ ? UK_CZ : UK_SWAP;
+                u.j0 = op.rb[0];
+                u.j1 = op.rb[1];
+                u.pad = 0;
+                u.mat = 0;
+                u.pad2 = 0;
+                put_uop(c.uops + nu++, u);
+            }
+            }
+        }
+        for (int jj = 0; jj < 8; ++jj) fuse_flush(c, jj, pend_set, nu, nm, flops);
+        c.ug[ng].gidx = (int)g;
+        c.ug[ng].a = first;
+        c.ug[ng].b = nu - first;
+        c.ug[ng].fallback = 0;
+        ++ng;
+        if (cut) {
+            S.end = o;
+            break;
+        }
+        j = b;
+    }
+    if (cut) S.stop = STOP_NONE;
+    S.n_ug = ng;
+    S.pass_flops = flops;
+}
+
 // ----------------------------------------------------------- reductions
 // Accumulate, over the tile, the squared norm and the candidate weights of
 // op `op` (Kraus: ||K_j v||^2; measure: outcome probabilities).
 template <class R>
-__device__ void reduce_tile(Ctx<R> &c, const DevOp &op, double (&acc)[kMaxRed])
+__device__ __noinline__ void reduce_tile(Ctx<R> &c, const DevOp &op, double (&acc)[kMaxRed])
 {
     using A = typename V2<R>::T;
     const ExecParams &P = c.P;
-    A *L = c.L;
+    lds<A> *L = c.L;
     if (op.kind == DK_KRAUS) {
         const DevRule &ru = P.rules[op.rule];
         const int nm = ru.n_terms;
@@ -443,7 +796,7 @@ __device__ void reduce_tile(Ctx<R> &c, const DevOp &op, double (&acc)[kMaxRed])
             const uint32_t b = op.lb[0], half = c.tsize >> 1;
             for (uint32_t p = c.tid; p < half; p += kWG) {
                 const uint32_t i0 = ins0(p, b), i1 = i0 | (1u << b);
-                const A a = L[i0], d = L[i1];
+                const A a = L[c.at(i0)], d = L[c.at(i1)];
                 const double ar = a.x, ai = a.y, dr = d.x, di = d.y;
                 acc[0] += fma(ar, ar, ai * ai) + fma(dr, dr, di * di);
 #pragma unroll
@@ -467,7 +820,7 @@ __device__ void reduce_tile(Ctx<R> &c, const DevOp &op, double (&acc)[kMaxRed])
                                          base | (1u << b0) | (1u << b1)};
                 double vr[4], vi[4];
                 for (int a = 0; a < 4; ++a) {
-                    const A v = L[idx[a]];
+                    const A v = L[c.at(idx[a])];
                     vr[a] = v.x;
                     vi[a] = v.y;
                     acc[0] += fma(vr[a], vr[a], vi[a] * vi[a]);
@@ -494,7 +847,7 @@ __device__ void reduce_tile(Ctx<R> &c, const DevOp &op, double (&acc)[kMaxRed])
         for (uint32_t i = c.tid; i < c.tsize; i += kWG) {
             uint32_t pat = 0;
             for (int t = 0; t < op.nq; ++t) pat |= ((i >> op.lb[t]) & 1u) << t;
-            const double w = abs2d(L[i]);
+            const double w = abs2d(L[c.at(i)]);
             acc[0] += w;
 #pragma unroll
             for (int o = 0; o < 16; ++o) acc[1 + o] += (pat == (uint32_t)o) ? w : 0.0;
@@ -504,7 +857,7 @@ __device__ void reduce_tile(Ctx<R> &c, const DevOp &op, double (&acc)[kMaxRed])
 
 // Sum acc[0..cnt) over the workgroup into S.red (fixed order).
 template <class R>
-__device__ void wg_reduce(Ctx<R> &c, double (&acc)[kMaxRed], int cnt)
+__device__ __noinline__ void wg_reduce(Ctx<R> &c, double (&acc)[kMaxRed], int cnt)
 {
     const int lane = c.tid & 63, wv = c.tid >> 6;
 #pragma unroll
@@ -559,47 +912,68 @@ __device__ void build_hi_off(Ctx<R> &c, const PassInfo &pi, int k)
     __syncthreads();
 }
 
+// Global <-> LDS tile copies in 16-byte chunks (two c64 or one c128
+// amplitude; the swizzle never touches bit 0, so a chunk stays contiguous),
+// eight independent loads in flight per thread.
 template <class R>
-__device__ void load_tile(Ctx<R> &c, const typename V2<R>::T *G, uint64_t base, bool fresh)
+__device__ void load_tile(Ctx<R> &c, const gbl<typename V2<R>::T> *G, uint64_t base, bool fresh)
 {
     using A = typename V2<R>::T;
     constexpr uint32_t V = 16 / sizeof(A);
-    for (uint32_t ch = c.tid; ch < c.tsize / V; ch += kWG) {
-        const uint32_t l = ch * V;
-        const uint64_t g = base + c.hi_off[l >> 4] + (l & 15u);
-        if (fresh) {
+    const uint32_t nch = c.tsize / V;
+    if (fresh) {
+        for (uint32_t ch = c.tid; ch < nch; ch += kWG) {
+            const uint32_t l = ch * V;
+            const uint64_t g = base + c.hi_off[l >> 4] + (l & 15u);
 #pragma unroll
             for (uint32_t v = 0; v < V; ++v) {
                 A z;
                 z.x = (g + v == 0) ? (R)1 : (R)0;
                 z.y = 0;
-                c.L[l + v] = z;
+                c.L[c.at(l + v)] = z;
             }
-        } else {
-            *(uint4 *)(c.L + l) = *(const uint4 *)(G + g);
+        }
+    } else if (nch % (8 * kWG) == 0) {
+        for (uint32_t ch0 = c.tid; ch0 < nch; ch0 += 8 * kWG) {
+            u32x4 x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t l = (ch0 + u * kWG) * V;
+                x[u] = *(const gbl<u32x4> *)(G + base + c.hi_off[l >> 4] + (l & 15u));
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t l = (ch0 + u * kWG) * V;
+                *(lds<u32x4> *)(c.L + c.at(l)) = x[u];
+            }
+        }
+    } else {
+        for (uint32_t ch = c.tid; ch < nch; ch += kWG) {
+            const uint32_t l = ch * V;
+            *(lds<u32x4> *)(c.L + c.at(l)) = *(const gbl<u32x4> *)(G + base + c.hi_off[l >> 4] + (l & 15u));
         }
     }
     __syncthreads();
 }
 
 template <class R>
-__device__ void store_tile(Ctx<R> &c, typename V2<R>::T *G, uint64_t base)
+__device__ void store_tile(Ctx<R> &c, gbl<typename V2<R>::T> *G, uint64_t base)
 {
     using A = typename V2<R>::T;
     constexpr uint32_t V = 16 / sizeof(A);
     for (uint32_t ch = c.tid; ch < c.tsize / V; ch += kWG) {
         const uint32_t l = ch * V;
         const uint64_t g = base + c.hi_off[l >> 4] + (l & 15u);
-        *(uint4 *)(G + g) = *(const uint4 *)(c.L + l);
+        *(gbl<u32x4> *)(G + g) = *(const lds<u32x4> *)(c.L + c.at(l));
     }
     __syncthreads();
 }
 
 template <class R>
-__device__ __forceinline__ typename V2<R>::T *slot_ptr(const ExecParams &P, int slot)
+__device__ __forceinline__ gbl<typename V2<R>::T> *slot_ptr(const ExecParams &P, int slot)
 {
     using A = typename V2<R>::T;
-    return (A *)P.slots + (size_t)slot * P.slot_amps;
+    return (gbl<A> *)P.slots + (size_t)slot * P.slot_amps;
 }
 
 // ----------------------------------------------------------- queue/slots
@@ -609,7 +983,7 @@ __device__ bool spin_expired(unsigned long long t0, unsigned long long limit)
 }
 
 // Thread 0 only.
-__device__ int slot_pop(const ExecParams &P)
+__device__ __noinline__ int slot_pop(const ExecParams &P)
 {
     Control *ctl = P.ctl;
     const unsigned long long t0 = wall_clock64();
@@ -631,7 +1005,7 @@ __device__ int slot_pop(const ExecParams &P)
     return s;
 }
 
-__device__ void slot_push(const ExecParams &P, int s)
+__device__ __noinline__ void slot_push(const ExecParams &P, int s)
 {
     Control *ctl = P.ctl;
     const unsigned long long t0 = wall_clock64();
@@ -654,7 +1028,7 @@ __device__ void slot_push(const ExecParams &P, int s)
 }
 
 // Thread 0 only: reserve a record, fill it, publish it.
-__device__ void queue_push(const ExecParams &P, const BranchRec &r)
+__device__ __noinline__ void queue_push(const ExecParams &P, const BranchRec &r)
 {
     Control *ctl = P.ctl;
     const uint32_t idx = atomicAdd(&ctl->q_tail, 1u);
@@ -679,7 +1053,7 @@ __device__ __forceinline__ int pauli_pick(const ExecParams &P, const DevRule &ru
 
 // First candidate whose running sum of S.red[1..] exceeds u*N; if rounding
 // leaves none, the last candidate with a non-zero weight.
-__device__ __forceinline__ int red_pick(const WgShared &S, int cnt, double u)
+__device__ __forceinline__ int red_pick(const lds<WgShared> &S, int cnt, double u)
 {
     const double x = u * S.red[0];
     double run = 0;
@@ -699,7 +1073,7 @@ __device__ __forceinline__ int red_count(const ExecParams &P, const DevOp &op)
 }
 
 // Record measured bits (with readout flips) of shot `shot`.
-__device__ void record_bits(const ExecParams &P, const DevOp &op, uint64_t shot, uint32_t o)
+__device__ __noinline__ void record_bits(const ExecParams &P, const DevOp &op, uint64_t shot, uint32_t o)
 {
     uint64_t m = P.memory[shot];
     for (int t = 0; t < op.nq; ++t) {
@@ -712,7 +1086,7 @@ __device__ void record_bits(const ExecParams &P, const DevOp &op, uint64_t shot,
 }
 
 // Outcome of shot `shot` at random op `op` (after its reduction, if any).
-__device__ __forceinline__ int outcome_of(const ExecParams &P, const WgShared &S,
+__device__ __forceinline__ int outcome_of(const ExecParams &P, const lds<WgShared> &S,
                                           const DevOp &op, uint64_t shot)
 {
     const double u = philox_u01(P.seed, shot, op.r, 0);
@@ -722,17 +1096,17 @@ __device__ __forceinline__ int outcome_of(const ExecParams &P, const WgShared &S
 
 // ----------------------------------------------------------- the kernel
 template <class R>
-__device__ void copy_state_to_slot(Ctx<R> &c, int dst, int src_slot, bool from_lds)
+__device__ __noinline__ void copy_state_to_slot(Ctx<R> &c, int dst, int src_slot, bool from_lds)
 {
     using A = typename V2<R>::T;
     const ExecParams &P = c.P;
-    A *D = slot_ptr<R>(P, dst);
+    gbl<A> *D = slot_ptr<R>(P, dst);
     const uint64_t namps = 1ull << P.n_qubits;
     if (from_lds) {
         for (uint64_t i = c.tid; i < namps; i += kWG) D[i] = c.L[i];
     } else {
-        const uint4 *Sp = (const uint4 *)slot_ptr<R>(P, src_slot);
-        uint4 *Dp = (uint4 *)D;
+        const gbl<u32x4> *Sp = (const gbl<u32x4> *)slot_ptr<R>(P, src_slot);
+        gbl<u32x4> *Dp = (gbl<u32x4> *)D;
         const uint64_t n16 = namps * sizeof(A) / 16;
         for (uint64_t i = c.tid; i < n16; i += kWG) Dp[i] = Sp[i];
     }
@@ -743,10 +1117,10 @@ __device__ void copy_state_to_slot(Ctx<R> &c, int dst, int src_slot, bool from_l
 // Partition the branch's shots by outcome at op j and continue with the
 // first group; other groups get a copied state (or the waiting list).
 template <class R>
-__device__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
+__device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
 {
     const ExecParams &P = c.P;
-    WgShared &S = c.S;
+    lds<WgShared> &S = c.S;
     const int tid = c.tid;
     const int m = S.hi - S.lo;
     const int chunk = (m + kWG - 1) / kWG;
@@ -861,10 +1235,10 @@ __device__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
 
 // Determine the op range of the next sweep (and why it stops).
 template <class R>
-__device__ void plan_pass(Ctx<R> &c)
+__device__ __noinline__ void plan_pass(Ctx<R> &c)
 {
     const ExecParams &P = c.P;
-    WgShared &S = c.S;
+    lds<WgShared> &S = c.S;
     const int tid = c.tid;
     const int start = S.cursor;
     const int m = S.hi - S.lo;
@@ -930,10 +1304,10 @@ __device__ void plan_pass(Ctx<R> &c)
             }
         }
         if (op.kind == DK_PAULI) {
-            atomicMin(&S.omin, lmin);
-            atomicMax(&S.omax, lmax);
+            atomicMin((int *)&S.omin, lmin);
+            atomicMax((int *)&S.omax, lmax);
         } else if (high) {
-            atomicOr(&S.anyhigh, 1);
+            atomicOr((int *)&S.anyhigh, 1);
         }
         __syncthreads();
         const int omin = S.omin, omax = S.omax, anyhigh = S.anyhigh;
@@ -962,6 +1336,9 @@ __device__ void plan_pass(Ctx<R> &c)
         S.stop = stop;
         S.stop_op = j;
         S.norm_lb = nlb;
+        S.n_ug = 0;
+        S.pass_flops = 0;
+        if (P.use_groups && !P.resident && j > start) build_uops(c);
     }
     __syncthreads();
 }
@@ -970,7 +1347,7 @@ template <class R>
 __device__ void apply_range(Ctx<R> &c, uint64_t &flops)
 {
     const ExecParams &P = c.P;
-    WgShared &S = c.S;
+    lds<WgShared> &S = c.S;
     for (int j = S.start; j < S.end; ++j) {
         const DevOp &op = P.ops[j];
         const int d = c.dec[j - S.start];
@@ -982,14 +1359,39 @@ __device__ void apply_range(Ctx<R> &c, uint64_t &flops)
 
 // One sweep over the state: apply [start, end), then accumulate the
 // reduction of the stopping op if asked.
-template <class R>
+template <class R, int NR>
+__device__ void run_groups(Ctx<R> &c, uint64_t &flops)
+{
+    const ExecParams &P = c.P;
+    lds<WgShared> &S = c.S;
+    for (int u = 0; u < S.n_ug; ++u) {
+        const lds<UGroup> &gl = c.ug[u];
+        UGroup g;
+        g.gidx = gl.gidx;
+        g.a = gl.a;
+        g.b = gl.b;
+        g.fallback = gl.fallback;
+        if (g.fallback) {
+            for (int o = g.a; o < g.b; ++o) {
+                const double s = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
+                apply_op(c, P.ops[o], c.dec[o - S.start], s);
+            }
+        } else if constexpr (NR > 0) {
+            run_group<R, NR>(c, P.groups[g.gidx], g.a, g.b);
+        }
+    }
+    flops += S.pass_flops;
+}
+
+template <class R, int NR>
 __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
 {
     using A = typename V2<R>::T;
     const ExecParams &P = c.P;
-    WgShared &S = c.S;
+    lds<WgShared> &S = c.S;
     const int n = P.n_qubits, k = P.tile_q;
     const bool has_ops = S.end > S.start;
+    const bool grp = NR > 0 && P.use_groups && !P.resident && has_ops;
     double acc[kMaxRed];
 #pragma unroll
     for (int v = 0; v < kMaxRed; ++v) acc[v] = 0;
@@ -1000,18 +1402,22 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
         if (want_reduce) reduce_tile(c, rop, acc);
     } else {
         const PassInfo &pi = P.passes[P.ops[S.start].pass];
+        c.swm = P.use_groups ? P.swz : 0u;
         build_hi_off(c, pi, k);
-        A *G = slot_ptr<R>(P, S.slot);
+        gbl<A> *G = slot_ptr<R>(P, S.slot);
         const bool fresh = S.fresh != 0;
         for (uint32_t t = 0; t < c.n_tiles; ++t) {
             const uint64_t base = tile_base<R>(pi, n, k, t);
             load_tile(c, G, base, fresh);
-            apply_range(c, flops);
+            if (grp) run_groups<R, NR>(c, flops);
+            else apply_range(c, flops);
             if (want_reduce) {
                 reduce_tile(c, rop, acc);
             }
             if (has_ops) store_tile(c, G, base);
         }
+        c.swm = 0;
+        if (grp) flops = S.pass_flops;
         if (c.tid == 0) {
             const uint64_t sb = (1ull << n) * sizeof(A);
             S.st[ST_PASSES] += 1;
@@ -1033,10 +1439,10 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
 // After a reduction for op j: each shot's outcome; continue with it, or
 // split the branch.
 template <class R>
-__device__ void decide(Ctx<R> &c)
+__device__ __noinline__ void decide(Ctx<R> &c)
 {
     const ExecParams &P = c.P;
-    WgShared &S = c.S;
+    lds<WgShared> &S = c.S;
     const int j = S.stop_op;
     const DevOp &op = P.ops[j];
     const int m = S.hi - S.lo;
@@ -1069,18 +1475,18 @@ __device__ void decide(Ctx<R> &c)
 // Final measurement of all qubits by sampling the shared state once per
 // shot: FP64 tile sums, tile search, in-tile prefix and search.
 template <class R>
-__device__ void terminal_sample(Ctx<R> &c)
+__device__ __noinline__ void terminal_sample(Ctx<R> &c)
 {
     using A = typename V2<R>::T;
     const ExecParams &P = c.P;
-    WgShared &S = c.S;
+    lds<WgShared> &S = c.S;
     const int n = P.n_qubits, k = P.tile_q;
     const int tid = c.tid;
     const DevOp &op = P.ops[S.stop_op];
-    double *D = (double *)c.L;  // in-place |a|^2 prefix, same bytes as the tile
+    lds<double> *D = (lds<double> *)c.L;  // in-place |a|^2 prefix, same bytes as the tile
     double *tsums = P.tile_sums + (size_t)blockIdx.x * c.n_tiles;
     const PassInfo &pi = P.passes[op.pass];
-    A *G = P.resident ? nullptr : slot_ptr<R>(P, S.slot);
+    gbl<A> *G = P.resident ? nullptr : slot_ptr<R>(P, S.slot);
     const uint32_t seg = c.tsize >= kWG ? c.tsize / kWG : 1;
 
     // in-tile: D[e] = inclusive prefix of |a|^2 in the tile (LDS)
@@ -1112,7 +1518,7 @@ __device__ void terminal_sample(Ctx<R> &c)
             }
         }
         // segment offsets (sequential over segments, fixed order)
-        double *off = (double *)c.cnt;   // kWG doubles
+        lds<double> *off = (lds<double> *)c.cnt;   // kWG doubles
         if (active) off[tid] = run; else if (tid < kWG) off[tid] = 0;
         __syncthreads();
         if (tid == 0) {
@@ -1226,11 +1632,11 @@ __device__ void terminal_sample(Ctx<R> &c)
 
 // Write the normalised state of this branch into P.dump (complex double).
 template <class R>
-__device__ void dump_state(Ctx<R> &c, const PassInfo &pi)
+__device__ __noinline__ void dump_state(Ctx<R> &c, const PassInfo &pi)
 {
     using A = typename V2<R>::T;
     const ExecParams &P = c.P;
-    WgShared &S = c.S;
+    lds<WgShared> &S = c.S;
     const int n = P.n_qubits, k = P.tile_q;
     double2 *out = (double2 *)P.dump;
     double a = 0;
@@ -1245,7 +1651,7 @@ __device__ void dump_state(Ctx<R> &c, const PassInfo &pi)
         __syncthreads();
         return;
     }
-    A *G = slot_ptr<R>(P, S.slot);
+    gbl<A> *G = slot_ptr<R>(P, S.slot);
     build_hi_off(c, pi, k);
     for (uint32_t t = 0; t < c.n_tiles; ++t) {
         load_tile(c, G, tile_base<R>(pi, n, k, t), S.fresh != 0);
@@ -1267,10 +1673,10 @@ __device__ void dump_state(Ctx<R> &c, const PassInfo &pi)
 }
 
 template <class R>
-__device__ void maybe_dump(Ctx<R> &c, int at_op)
+__device__ __noinline__ void maybe_dump(Ctx<R> &c, int at_op)
 {
     const ExecParams &P = c.P;
-    WgShared &S = c.S;
+    lds<WgShared> &S = c.S;
     if (P.dump_shot < 0 || P.dump == nullptr) return;
     if (c.tid == 0) S.dump_here = 0;
     __syncthreads();
@@ -1282,23 +1688,32 @@ __device__ void maybe_dump(Ctx<R> &c, int at_op)
     dump_state(c, P.passes[pidx]);
 }
 
-template <class R>
+template <class R, int NR>
 __global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
 {
     using A = typename V2<R>::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ WgShared S;
+    __shared__ WgShared S_;
+    lds<WgShared> &S = *(lds<WgShared> *)&S_;
     const int tid = threadIdx.x;
     const int n = P.n_qubits, k = P.tile_q;
     Ctx<R> c{P, S};
     c.tid = tid;
+    c.k = k;
+    c.swm = 0;
     c.tsize = 1u << k;
     c.n_tiles = P.resident ? 1u : (1u << (n - k));
-    c.L = (A *)smem;
-    c.hi_off = (uint32_t *)(smem + (size_t)c.tsize * sizeof(A));
+    lds<unsigned char> *sm = (lds<unsigned char> *)smem;
+    c.L = (lds<A> *)sm;
+    c.hi_off = (lds<uint32_t> *)(sm + (size_t)c.tsize * sizeof(A));
     const uint32_t n_hi = P.resident ? 4u : (1u << (k - kCoalesceQ));
-    c.dec = (int *)(c.hi_off + n_hi);
-    c.cnt = c.dec + kMaxPassOps;
+    c.dec = (lds<int> *)(c.hi_off + n_hi);
+    lds<unsigned char> *uarea = (lds<unsigned char> *)(c.dec + kMaxPassOps);
+    c.cnt = (lds<int> *)uarea;
+    c.ug = (lds<UGroup> *)uarea;
+    c.uops = (lds<UOp> *)(uarea + kMaxPassGroups * sizeof(UGroup));
+    c.mats = (lds<R> *)((lds<unsigned char> *)c.uops + kMaxPassUops * sizeof(UOp));
+    c.pend = (lds<double> *)((lds<unsigned char> *)c.mats + kMaxPassMats * 8 * sizeof(R));
     if (tid < ST_COUNT) S.st[tid] = 0;
     __syncthreads();
 
@@ -1314,7 +1729,15 @@ __global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
                         // poll relaxed; one acquire fence once the record is published
                         if (ld_rlx(&P.ready[t])) {
                             __atomic_thread_fence(__ATOMIC_ACQUIRE);
-                            S.rec = P.queue[t];
+                            const BranchRec q = P.queue[t];
+                            S.rec.slot = q.slot;
+                            S.rec.lo = q.lo;
+                            S.rec.hi = q.hi;
+                            S.rec.cursor = q.cursor;
+                            S.rec.pending = q.pending;
+                            S.rec.flags = q.flags;
+                            S.rec.scale = q.scale;
+                            S.rec.norm_lb = q.norm_lb;
                             S.status = ST_WORK;
                             break;
                         }
@@ -1360,7 +1783,7 @@ __global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
                     c.L[i] = z;
                 }
             } else {
-                const A *G = slot_ptr<R>(P, S.slot);
+                const gbl<A> *G = slot_ptr<R>(P, S.slot);
                 for (uint32_t i = tid; i < c.tsize; i += kWG) c.L[i] = G[i];
             }
             __syncthreads();
@@ -1374,7 +1797,7 @@ __global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
             plan_pass(c);
             const int stop = S.stop;
             if (stop == STOP_TERMINAL || stop == STOP_END) {
-                if (S.end > S.start) run_sweep(c, false);
+                if (S.end > S.start) run_sweep<R, NR>(c, false);
                 if (tid == 0) { S.cursor = S.end; S.pending = -1; }
                 __syncthreads();
                 maybe_dump(c, S.cursor);
@@ -1389,7 +1812,7 @@ __global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
                 if (tid == 0) atomicOr(&P.ctl->error, kErrState);
                 break;
             }
-            if (S.end > S.start || stop == STOP_REDUCE) run_sweep(c, stop == STOP_REDUCE);
+            if (S.end > S.start || stop == STOP_REDUCE) run_sweep<R, NR>(c, stop == STOP_REDUCE);
             if (stop == STOP_NONE) {
                 if (tid == 0) { S.cursor = S.end; S.pending = -1; }
                 __syncthreads();
@@ -1486,6 +1909,23 @@ __global__ void restart_kernel(ExecParams P, int n_wait)
 }  // namespace svb
 
 // ------------------------------------------------------------ launchers
+static size_t uarea_bytes(int amp_bytes)
+{
+    const size_t real = amp_bytes / 2;
+    const size_t fuse = svb::kMaxPassGroups * sizeof(svb::UGroup) + svb::kMaxPassUops * sizeof(svb::UOp) +
+                        svb::kMaxPassMats * 8 * real + 8 * 8 * sizeof(double);
+    const size_t cnt = 16 * svb::kWG * 4;
+    return fuse > cnt ? fuse : cnt;
+}
+
+extern "C" size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident)
+{
+    const size_t tile = ((size_t)1 << tile_q) * amp_bytes;
+    const size_t hi = resident ? 4 * 4 : ((size_t)1 << (tile_q - svb::kCoalesceQ)) * 4;
+    const size_t dec = svb::kMaxPassOps * 4;
+    return tile + hi + dec + uarea_bytes(amp_bytes);
+}
+
 extern "C" {
 
 hipError_t svb_launch_init(const svb::ExecParams *P, int restart, int n_root, int root_slot,
@@ -1502,50 +1942,48 @@ hipError_t svb_launch_restart(const svb::ExecParams *P, int n_wait, hipStream_t 
     return hipGetLastError();
 }
 
-size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident)
-{
-    const size_t tile = ((size_t)1 << tile_q) * amp_bytes;
-    const size_t hi = resident ? 4 * 4 : ((size_t)1 << (tile_q - svb::kCoalesceQ)) * 4;
-    const size_t dec = svb::kMaxPassOps * 4;
-    const size_t cnt = 16 * svb::kWG * 4;
-    return tile + hi + dec + cnt;
-}
+}  // extern "C"
 
-hipError_t svb_launch_exec(const svb::ExecParams *P, int is_c128, int workers, hipStream_t st)
+template <class R, int NR>
+static hipError_t launch_one(const svb::ExecParams *P, int workers, size_t lds, hipStream_t st,
+                             int *occ)
 {
-    const size_t lds = svb_exec_lds_bytes(P->tile_q, is_c128 ? 16 : 8, P->resident);
-    if (is_c128) {
-        hipError_t e = hipFuncSetAttribute((const void *)svb::exec_kernel<double>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(svb::exec_kernel<double>, dim3(workers), dim3(svb::kWG), lds, st, *P);
-    } else {
-        hipError_t e = hipFuncSetAttribute((const void *)svb::exec_kernel<float>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(svb::exec_kernel<float>, dim3(workers), dim3(svb::kWG), lds, st, *P);
-    }
+    hipError_t e = hipFuncSetAttribute((const void *)svb::exec_kernel<R, NR>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (occ)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, svb::exec_kernel<R, NR>, svb::kWG,
+                                                            lds);
+    hipLaunchKernelGGL((svb::exec_kernel<R, NR>), dim3(workers), dim3(svb::kWG), lds, st, *P);
     return hipGetLastError();
 }
 
-hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int *blocks_per_cu)
+static hipError_t dispatch(const svb::ExecParams *P, int is_c128, int reg_bits, int tile_q,
+                           int resident, int workers, hipStream_t st, int *occ)
 {
     const size_t lds = svb_exec_lds_bytes(tile_q, is_c128 ? 16 : 8, resident);
-    hipError_t e;
     if (is_c128) {
-        e = hipFuncSetAttribute((const void *)svb::exec_kernel<double>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, svb::exec_kernel<double>,
-                                                         svb::kWG, lds);
-    } else {
-        e = hipFuncSetAttribute((const void *)svb::exec_kernel<float>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, svb::exec_kernel<float>,
-                                                         svb::kWG, lds);
+        if (reg_bits == 5) return launch_one<double, 32>(P, workers, lds, st, occ);
+        if (reg_bits == 4) return launch_one<double, 16>(P, workers, lds, st, occ);
+        return launch_one<double, 0>(P, workers, lds, st, occ);
     }
-    return e;
+    if (reg_bits == 6) return launch_one<float, 64>(P, workers, lds, st, occ);
+    if (reg_bits == 5) return launch_one<float, 32>(P, workers, lds, st, occ);
+    return launch_one<float, 0>(P, workers, lds, st, occ);
+}
+
+extern "C" {
+
+hipError_t svb_launch_exec(const svb::ExecParams *P, int is_c128, int reg_bits, int workers,
+                           hipStream_t st)
+{
+    return dispatch(P, is_c128, reg_bits, P->tile_q, P->resident, workers, st, nullptr);
+}
+
+hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int reg_bits,
+                              int *blocks_per_cu)
+{
+    return dispatch(nullptr, is_c128, reg_bits, tile_q, resident, 0, nullptr, blocks_per_cu);
 }
 
 }  // extern "C"

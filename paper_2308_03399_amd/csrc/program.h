@@ -7,7 +7,10 @@
 namespace svb {
 
 constexpr int kWG = 256;             // threads per executor workgroup
-constexpr int kMaxPassOps = 1024;    // ops applied in one tile sweep
+constexpr int kMaxPassOps = 512;     // ops applied in one tile sweep
+constexpr int kMaxPassGroups = 64;   // register groups in one sweep
+constexpr int kMaxPassUops = 512;    // register micro-ops in one sweep
+constexpr int kMaxPassMats = 256;    // fused 2x2 matrices in one sweep
 constexpr int kMaxKraus = 8;         // matrices per Kraus channel
 constexpr int kMaxMeasQ = 4;         // qubits of a non-terminal measure
 constexpr int kMaxRed = 1 + 16;      // norm + up to 16 outcome sums
@@ -41,10 +44,23 @@ struct DevOp {
     uint32_t pass;       // static pass holding this op
     uint32_t mat;        // pool offset (doubles) of this op's matrix
     uint32_t rule;       // noise rule index (DK_PAULI / DK_KRAUS)
-    uint32_t pad;
+    uint32_t group;      // register group holding this op
     uint8_t q[8];        // physical qubits
     uint8_t lb[8];       // tile-local bit of each qubit in its static pass
+    uint8_t rb[8];       // register bit of each qubit in its group
     uint8_t c[32];       // clbits (terminal measure: clbit of qubit t)
+};
+
+// A register group: consecutive ops of a pass whose qubits lie on at most
+// r = log2(amplitudes per thread) tile bits. Each thread gathers the 2^r
+// amplitudes that differ in those bits from LDS into registers, applies the
+// group's ops there and scatters them back.
+struct GroupInfo {
+    uint32_t first_op, end_op;  // ops [first_op, end_op)
+    uint32_t fallback;          // 1: ops run as LDS sweeps (measure, 4x4 ops)
+    uint32_t pad;
+    uint8_t gpos[8];            // register bit j -> tile bit
+    uint8_t cpos[16];           // thread-index bit i -> tile bit
 };
 
 // Per-rule channel data in the pool.
@@ -110,6 +126,7 @@ struct ExecParams {
     const DevOp *ops;
     const PassInfo *passes;
     const DevRule *rules;
+    const GroupInfo *groups;
     const double *pool;
     void *slots;             // n_slots states, slot_amps amplitudes apart
     uint64_t slot_amps;
@@ -136,6 +153,8 @@ struct ExecParams {
     int32_t branch_mode;     // 1: shots may split (work queue with pushes)
     int32_t private_slots;   // 1: worker w uses slot w (batch mode, n > k)
     int32_t resident;        // 1: whole state in LDS (n <= k)
+    int32_t use_groups;      // 1: streamed passes run register groups
+    uint32_t swz;            // LDS swizzle mask of streamed passes
 };
 
 }  // namespace svb

@@ -27,8 +27,10 @@ extern "C" {
 hipError_t svb_launch_init(const ExecParams *P, int restart, int n_root, int root_slot,
                            int n_free, hipStream_t st);
 hipError_t svb_launch_restart(const ExecParams *P, int n_wait, hipStream_t st);
-hipError_t svb_launch_exec(const ExecParams *P, int is_c128, int workers, hipStream_t st);
-hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int *blocks_per_cu);
+hipError_t svb_launch_exec(const ExecParams *P, int is_c128, int reg_bits, int workers,
+                           hipStream_t st);
+hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int reg_bits,
+                              int *blocks_per_cu);
 size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident);
 hipError_t svb_counts(const uint64_t *memory, int64_t n, void *temp, size_t temp_bytes,
                       uint64_t *keys_sorted, uint64_t *uniq, uint32_t *cnt, uint32_t *n_uniq,
@@ -73,6 +75,8 @@ struct sv_batch {
     int64_t spin_ms = 300000;
     // derived
     int tile_q = 0, resident = 0, workers = 0, slots = 0;
+    int use_groups = 0, reg_bits = 0;  // register-group engine, log2(amps per thread)
+    int64_t opt_engine = 0;            // 0 automatic, 1 LDS sweeps only
     int cus = 0;
     int64_t wallclock_khz = 100000;
     // arena
@@ -121,8 +125,13 @@ static sv_status derive(sv_batch *b)
         b->resident = 0;
         b->tile_q = k;
     }
+    // register groups need 2^k = kWG * 2^r amplitudes per tile
+    const int r = b->tile_q - 8;
+    const bool r_ok = b->dtype == SV_C128 ? (r == 4 || r == 5) : (r == 5 || r == 6);
+    b->use_groups = (!b->resident && r_ok && b->opt_engine == 0) ? 1 : 0;
+    b->reg_bits = b->use_groups ? r : 0;
     int per_cu = 0;
-    HIPCHK(svb_exec_occupancy(b->dtype == SV_C128, b->tile_q, b->resident, &per_cu));
+    HIPCHK(svb_exec_occupancy(b->dtype == SV_C128, b->tile_q, b->resident, b->reg_bits, &per_cu));
     if (per_cu < 1) return fail(SV_EDEVICE, "executor does not fit on a compute unit");
     int64_t w = b->opt_workers > 0 ? b->opt_workers : (int64_t)per_cu * b->cus;
     if (b->mode == SV_MODE_BATCH) w = std::min<int64_t>(w, b->shots);
@@ -364,51 +373,239 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
     return SV_OK;
 }
 
-// Static pass plan: consecutive ops whose qubits (plus qubits 0..3) fit in
-// k tile qubits. The final measurement of all qubits gets a pass of its own
-// with tile qubits 0..k-1 (contiguous chunks for sampling).
-static void plan_passes(int n, int k, bool resident, const std::vector<XOp> &xo, bool terminal,
-                        std::vector<PassInfo> &passes, std::vector<uint32_t> &op_pass)
+// ------------------------------------------------------------------ planner
+// Ops may be executed in any order that keeps (a) the order of ops sharing a
+// qubit and (b) the relative order of the state-dependent random ops (Kraus
+// channels, measure, reset). Unitaries and drawn Pauli strings on other
+// qubits commute with a Kraus or measure op and do not change its outcome
+// probabilities, so every per-shot decision is unchanged by such a reorder.
+//
+// Passes: greedy in list order, an op joins the current pass if all its
+// predecessors are already placed and its qubits fit in the k tile qubits
+// (which always include qubits 0..3, so global accesses are 128-byte runs).
+// Groups: the same greedy inside a pass with r = log2(amplitudes per
+// thread) register bits. Measures and dense 4x4 ops form groups of their own
+// that run as LDS sweeps. The final measurement of all qubits gets a pass of
+// its own with tile qubits 0..k-1 (contiguous chunks for sampling).
+struct Plan {
+    std::vector<uint32_t> order;  // device position -> expanded index
+    std::vector<PassInfo> passes;
+    std::vector<GroupInfo> groups;
+    std::vector<uint32_t> op_pass, op_group;  // per device position
+};
+
+static bool op_ordered(const XOp &x)
 {
-    passes.clear();
-    op_pass.assign(xo.size(), 0);
-    auto finish = [&](uint32_t first, uint32_t end, uint32_t mask) {
-        // pad with the lowest unused qubits
-        for (int q = 0; q < n && __builtin_popcount(mask) < k; ++q) mask |= 1u << q;
+    return x.kind == -2 || x.kind == SV_OP_MEASURE || x.kind == SV_OP_RESET ||
+           x.kind == SV_OP_MEASURE_RESET;
+}
+
+static bool op_fallback(const XOp &x, const std::vector<Rule> &rules)
+{
+    if (x.kind == SV_OP_MEASURE || x.kind == SV_OP_RESET || x.kind == SV_OP_MEASURE_RESET) return true;
+    if (x.kind == SV_OP_UNITARY && x.q.size() == 2) return true;
+    if (x.kind == -2 && rules[x.rule].nq == 2) return true;
+    return false;
+}
+
+static uint32_t qmask_of(const XOp &x)
+{
+    uint32_t m = 0;
+    for (int q : x.q) m |= 1u << q;
+    return m;
+}
+
+// effect of tile bit b on the low six bits of its swizzled LDS position
+static uint32_t fold_vec(int b, uint32_t swz)
+{
+    if (b < 6) return 1u << b;
+    if (b < 12) return (1u << (b - 6)) & swz;
+    return (1u << (b - 12)) & swz;
+}
+
+static int gf2_rank_add(uint32_t basis[6], uint32_t v)
+{
+    for (int i = 5; i >= 0; --i) {
+        if (!((v >> i) & 1)) continue;
+        if (!basis[i]) {
+            basis[i] = v;
+            return 1;
+        }
+        v ^= basis[i];
+    }
+    return 0;
+}
+
+static void plan_program(int n, int k, int r, bool resident, bool use_groups, uint32_t swz,
+                         const std::vector<XOp> &xo, const std::vector<Rule> &rules,
+                         bool terminal, Plan &P)
+{
+    P = Plan();
+    const uint32_t N = (uint32_t)xo.size();
+    const uint32_t body = terminal ? N - 1 : N;
+    const uint32_t all = (n >= 32) ? 0xffffffffu : ((1u << n) - 1);
+    const uint32_t base_mask = resident ? all : ((1u << kCoalesceQ) - 1);
+    std::vector<uint32_t> remaining(body);
+    for (uint32_t j = 0; j < body; ++j) remaining[j] = j;
+
+    auto emit_pass = [&](const std::vector<uint32_t> &sel, uint32_t tmask) {
+        for (int q = 0; q < n && __builtin_popcount(tmask) < k; ++q) tmask |= 1u << q;
         PassInfo pi;
         std::memset(&pi, 0, sizeof pi);
-        pi.first_op = first;
-        pi.end_op = end;
-        pi.tmask = mask;
+        pi.first_op = (uint32_t)P.order.size();
+        pi.tmask = tmask;
+        int a = 0, g = 0, lbit[32];
+        for (int q = 0; q < n; ++q) {
+            if ((tmask >> q) & 1) {
+                lbit[q] = a;
+                pi.tq[a++] = (uint8_t)q;
+            } else {
+                lbit[q] = -1;
+                pi.gq[g++] = (uint8_t)q;
+            }
+        }
+        pi.contiguous = (tmask == (k >= 32 ? 0xffffffffu : ((1u << k) - 1)));
+        const uint32_t pidx = (uint32_t)P.passes.size();
+        // groups inside the pass
+        std::vector<uint32_t> grem = sel;
+        while (!grem.empty()) {
+            std::vector<uint32_t> gsel, grest;
+            uint32_t G = 0, blocked = 0;
+            bool ord_blocked = false, fb_group = false;
+            for (size_t idx = 0; idx < grem.size(); ++idx) {
+                const uint32_t j = grem[idx];
+                const XOp &x = xo[j];
+                const uint32_t m = qmask_of(x);
+                const bool ord = op_ordered(x);
+                const bool ok = !(m & blocked) && !(ord && ord_blocked);
+                const bool fb = !use_groups || op_fallback(x, rules);
+                if (fb) {
+                    if (ok && gsel.empty()) {
+                        gsel.push_back(j);
+                        fb_group = true;
+                        for (size_t t = idx + 1; t < grem.size(); ++t) grest.push_back(grem[t]);
+                        break;
+                    }
+                    blocked |= m;
+                    ord_blocked |= ord;
+                    grest.push_back(j);
+                    continue;
+                }
+                if (ok && __builtin_popcount(G | m) <= r) {
+                    gsel.push_back(j);
+                    G |= m;
+                } else {
+                    blocked |= m;
+                    ord_blocked |= ord;
+                    grest.push_back(j);
+                }
+            }
+            GroupInfo gi;
+            std::memset(&gi, 0, sizeof gi);
+            gi.first_op = (uint32_t)P.order.size();
+            gi.fallback = fb_group ? 1u : 0u;
+            if (!fb_group && use_groups) {
+                // register bits: the group's tile bits, then padding; lanes:
+                // tile bits whose swizzled positions spread over the banks
+                uint32_t reg_tile = 0;
+                for (int q = 0; q < n; ++q)
+                    if ((G >> q) & 1) reg_tile |= 1u << lbit[q];
+                std::vector<int> cand;
+                for (int b = 0; b < k; ++b)
+                    if (!((reg_tile >> b) & 1)) cand.push_back(b);
+                uint32_t basis[6] = {0, 0, 0, 0, 0, 0};
+                std::vector<int> lanes, others;
+                for (int b : cand) {
+                    if ((int)lanes.size() < 6 && gf2_rank_add(basis, fold_vec(b, swz)))
+                        lanes.push_back(b);
+                    else
+                        others.push_back(b);
+                }
+                // padding of the register bits comes from bits not used as lanes
+                std::vector<int> regs;
+                for (int b = 0; b < k; ++b)
+                    if ((reg_tile >> b) & 1) regs.push_back(b);
+                std::vector<int> rest2;
+                for (int b : others) {
+                    if ((int)regs.size() < r) regs.push_back(b);
+                    else rest2.push_back(b);
+                }
+                while ((int)lanes.size() < 6 && !rest2.empty()) {
+                    lanes.push_back(rest2.front());
+                    rest2.erase(rest2.begin());
+                }
+                std::sort(regs.begin(), regs.end());
+                for (int j = 0; j < r; ++j) gi.gpos[j] = (uint8_t)regs[j];
+                int ci = 0;
+                for (int b : lanes) gi.cpos[ci++] = (uint8_t)b;
+                for (int b : rest2) gi.cpos[ci++] = (uint8_t)b;
+            }
+            const uint32_t gidx = (uint32_t)P.groups.size();
+            for (uint32_t j : gsel) {
+                P.order.push_back(j);
+                P.op_pass.push_back(pidx);
+                P.op_group.push_back(gidx);
+            }
+            gi.end_op = (uint32_t)P.order.size();
+            P.groups.push_back(gi);
+            grem.swap(grest);
+        }
+        pi.end_op = (uint32_t)P.order.size();
+        P.passes.push_back(pi);
+    };
+
+    while (!remaining.empty()) {
+        std::vector<uint32_t> sel, rest;
+        uint32_t T = base_mask, blocked = 0;
+        bool ord_blocked = false;
+        for (size_t idx = 0; idx < remaining.size(); ++idx) {
+            const uint32_t j = remaining[idx];
+            if (sel.size() >= (size_t)kMaxPassOps) {
+                rest.insert(rest.end(), remaining.begin() + idx, remaining.end());
+                break;
+            }
+            const XOp &x = xo[j];
+            const uint32_t m = qmask_of(x);
+            const bool ord = op_ordered(x);
+            const bool ok = !(m & blocked) && !(ord && ord_blocked) &&
+                            __builtin_popcount(T | m) <= k;
+            if (ok) {
+                sel.push_back(j);
+                T |= m;
+            } else {
+                blocked |= m;
+                ord_blocked |= ord;
+                rest.push_back(j);
+            }
+        }
+        emit_pass(sel, T);
+        remaining.swap(rest);
+    }
+    if (terminal) {
+        // final measure-all: one op, contiguous tiles, its own fallback group
+        PassInfo pi;
+        std::memset(&pi, 0, sizeof pi);
+        pi.first_op = (uint32_t)P.order.size();
+        const uint32_t tm = resident ? all : ((1u << k) - 1);
+        pi.tmask = tm;
         int a = 0, g = 0;
         for (int q = 0; q < n; ++q) {
-            if ((mask >> q) & 1) pi.tq[a++] = (uint8_t)q;
+            if ((tm >> q) & 1) pi.tq[a++] = (uint8_t)q;
             else pi.gq[g++] = (uint8_t)q;
         }
-        pi.contiguous = (mask == ((k >= 32) ? 0xffffffffu : ((1u << k) - 1)));
-        for (uint32_t j = first; j < end; ++j) op_pass[j] = (uint32_t)passes.size();
-        passes.push_back(pi);
-    };
-    const uint32_t N = (uint32_t)xo.size();
-    if (resident) {
-        finish(0, N, (n >= 32) ? 0xffffffffu : ((1u << n) - 1));
-        return;
+        pi.contiguous = 1;
+        GroupInfo gi;
+        std::memset(&gi, 0, sizeof gi);
+        gi.first_op = pi.first_op;
+        gi.fallback = 1;
+        P.order.push_back(N - 1);
+        P.op_pass.push_back((uint32_t)P.passes.size());
+        P.op_group.push_back((uint32_t)P.groups.size());
+        gi.end_op = (uint32_t)P.order.size();
+        P.groups.push_back(gi);
+        pi.end_op = (uint32_t)P.order.size();
+        P.passes.push_back(pi);
     }
-    const uint32_t base_mask = (1u << kCoalesceQ) - 1;
-    const uint32_t body_end = terminal ? N - 1 : N;
-    uint32_t first = 0, mask = base_mask;
-    for (uint32_t j = 0; j < body_end; ++j) {
-        uint32_t m = 0;
-        for (int q : xo[j].q) m |= 1u << q;
-        if (__builtin_popcount(mask | m) > k) {
-            finish(first, j, mask);
-            first = j;
-            mask = base_mask;
-        }
-        mask |= m;
-    }
-    if (body_end > first) finish(first, body_end, mask);
-    if (terminal) finish(N - 1, N, (1u << k) - 1);
 }
 
 static void rule_dev(const Rule &R, std::vector<double> &pool, DevRule &d)
@@ -509,7 +706,7 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
     if (!b || !key) return fail(SV_EINVAL, "NULL argument");
     const std::string k = key;
     const bool sizing = k == "mode" || k == "slots" || k == "workers" || k == "tile_qubits" ||
-                        k == "program_bytes" || k == "dump_shot";
+                        k == "program_bytes" || k == "dump_shot" || k == "engine";
     if (sizing && b->attached) return fail(SV_ESTATE, "option %s must be set before attach", key);
     if (k == "mode") {
         if (v < 0 || v > 2) return fail(SV_EINVAL, "mode %lld", (long long)v);
@@ -530,6 +727,9 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
     } else if (k == "dump_shot") {
         if (v < -1 || v >= b->shots) return fail(SV_EINVAL, "dump_shot %lld", (long long)v);
         b->dump_shot = v;
+    } else if (k == "engine") {
+        if (v < 0 || v > 1) return fail(SV_EINVAL, "engine %lld (0 automatic, 1 LDS sweeps)", (long long)v);
+        b->opt_engine = v;
     } else if (k == "spin_limit_ms") {
         if (v < 1) return fail(SV_EINVAL, "spin_limit_ms %lld", (long long)v);
         b->spin_ms = v;
@@ -608,27 +808,36 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     if (!b->attached) return fail(SV_ESTATE, "no arena attached");
 
     // device program
-    std::vector<PassInfo> passes;
-    std::vector<uint32_t> op_pass;
-    plan_passes(n, b->tile_q, b->resident, xo, terminal, passes, op_pass);
+    Plan plan;
+    const uint32_t swz = b->dtype == SV_C128 ? 63u : 62u;
+    plan_program(n, b->tile_q, b->reg_bits, b->resident != 0, b->use_groups != 0, swz, xo, rules,
+                 terminal, plan);
+    const std::vector<PassInfo> &passes = plan.passes;
     std::vector<double> pool;
     std::vector<DevRule> drules(rules.size());
     for (size_t r = 0; r < rules.size(); ++r) rule_dev(rules[r], pool, drules[r]);
     std::vector<DevOp> dops(xo.size());
-    for (size_t j = 0; j < xo.size(); ++j) {
+    for (size_t pos = 0; pos < plan.order.size(); ++pos) {
+        const uint32_t j = plan.order[pos];
         const XOp &x = xo[j];
-        DevOp &d = dops[j];
+        DevOp &d = dops[pos];
         std::memset(&d, 0, sizeof d);
-        d.r = (uint32_t)j;
-        d.pass = op_pass[j];
+        d.r = j;
+        d.pass = plan.op_pass[pos];
+        d.group = plan.op_group[pos];
         d.nq = (uint8_t)x.q.size();
         const PassInfo &pi = passes[d.pass];
+        const GroupInfo &gi = plan.groups[d.group];
         for (size_t t = 0; t < x.q.size() && t < 8; ++t) {
             d.q[t] = (uint8_t)x.q[t];
             int lb = 0;
             for (int a = 0; a < b->tile_q && a < 16; ++a)
                 if (pi.tq[a] == x.q[t]) lb = a;
             d.lb[t] = (uint8_t)(b->resident ? x.q[t] : lb);
+            int rb = 0;
+            for (int a = 0; a < b->reg_bits && a < 8; ++a)
+                if (gi.gpos[a] == d.lb[t]) rb = a;
+            d.rb[t] = (uint8_t)rb;
         }
         if (x.kind == -1 || x.kind == -2) {
             d.kind = x.kind == -1 ? DK_PAULI : DK_KRAUS;
@@ -665,14 +874,18 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     const uint64_t pass_bytes = align_up(passes.size() * sizeof(PassInfo), 256);
     const uint64_t rule_bytes = align_up(std::max<size_t>(drules.size(), 1) * sizeof(DevRule), 256);
     const uint64_t pool_bytes = align_up(pool.size() * sizeof(double), 256);
-    if (ops_bytes + pass_bytes + rule_bytes + pool_bytes > (uint64_t)b->program_bytes)
+    const uint64_t grp_bytes = align_up(plan.groups.size() * sizeof(GroupInfo), 256);
+    const uint64_t prog_total = ops_bytes + pass_bytes + rule_bytes + pool_bytes + grp_bytes;
+    if (prog_total > (uint64_t)b->program_bytes)
         return fail(SV_ENOMEM, "program needs %llu bytes; raise option program_bytes",
-                    (unsigned long long)(ops_bytes + pass_bytes + rule_bytes + pool_bytes));
-    std::vector<char> blob(ops_bytes + pass_bytes + rule_bytes + pool_bytes, 0);
+                    (unsigned long long)prog_total);
+    std::vector<char> blob(prog_total, 0);
     std::memcpy(blob.data(), dops.data(), dops.size() * sizeof(DevOp));
     std::memcpy(blob.data() + ops_bytes, passes.data(), passes.size() * sizeof(PassInfo));
     if (!drules.empty()) std::memcpy(blob.data() + ops_bytes + pass_bytes, drules.data(), drules.size() * sizeof(DevRule));
     std::memcpy(blob.data() + ops_bytes + pass_bytes + rule_bytes, pool.data(), pool.size() * sizeof(double));
+    std::memcpy(blob.data() + ops_bytes + pass_bytes + rule_bytes + pool_bytes, plan.groups.data(),
+                plan.groups.size() * sizeof(GroupInfo));
     char *A = b->arena;
     const auto &L = b->lay;
     HIPCHK(hipMemcpyAsync(A + L.prog, blob.data(), blob.size(), hipMemcpyHostToDevice, b->stream));
@@ -683,6 +896,7 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     P.passes = (const PassInfo *)(A + L.prog + ops_bytes);
     P.rules = (const DevRule *)(A + L.prog + ops_bytes + pass_bytes);
     P.pool = (const double *)(A + L.prog + ops_bytes + pass_bytes + rule_bytes);
+    P.groups = (const GroupInfo *)(A + L.prog + ops_bytes + pass_bytes + rule_bytes + pool_bytes);
     P.slots = A + L.slots;
     P.slot_amps = 1ull << n;
     P.tile_sums = (double *)(A + L.tile_sums);
@@ -709,6 +923,8 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     P.branch_mode = b->mode == SV_MODE_BRANCH;
     P.private_slots = (!b->resident && b->mode == SV_MODE_BATCH) ? 1 : 0;
     P.resident = b->resident;
+    P.use_groups = b->use_groups;
+    P.swz = swz;
 
     const bool branch = P.branch_mode != 0;
     const int root_slot = (branch && !b->resident) ? 0 : -1;
@@ -718,7 +934,7 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     HIPCHK(hipEventRecord(b->ev0, b->stream));
     HIPCHK(svb_launch_init(&P, 0, (int)b->shots, root_slot, n_free, b->stream));
     for (;;) {
-        HIPCHK(svb_launch_exec(&P, b->dtype == SV_C128, b->workers, b->stream));
+        HIPCHK(svb_launch_exec(&P, b->dtype == SV_C128, b->reg_bits, b->workers, b->stream));
         Control ctl;
         HIPCHK(hipMemcpyAsync(&ctl, P.ctl, sizeof ctl, hipMemcpyDeviceToHost, b->stream));
         HIPCHK(hipStreamSynchronize(b->stream));

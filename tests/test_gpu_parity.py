@@ -119,3 +119,49 @@ def test_c64_agreement_and_tvd():
     say(f"c64 agreement {agree:.5f}")
     assert agree >= 0.995
     assert tvd_counts(got["memory"], exp) <= 5e-3
+
+
+# ---------------------------------------------------------------------------
+# Register-group engine (tiles of 2^k with k = 8 + log2(amplitudes/thread))
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,tile,n", [("c64", 14, 16), ("c64", 13, 15),
+                                          ("c128", 13, 15), ("c128", 12, 14)])
+def test_group_engine_matches_oracle(dtype, tile, n):
+    circ = W.random_layered(n, 5, seed=21, mid_measure=(2, (0, n - 1)))
+    noise = _noise_full(p1=0.02, p2=0.04, gamma=0.03)
+    shots = 64
+    say(f"case groups dtype={dtype} tile={tile} n={n} shots={shots}")
+    got = gpu_run(circ, noise, shots, dtype=dtype, seed=5, tile_qubits=tile)
+    exp = oracle_memory(circ, noise, shots, seed=5)
+    st = got["stats"]
+    assert st["tile_qubits"] == tile
+    bad = mismatches(got["memory"], exp)
+    if dtype == "c128":
+        assert bad == 0
+    else:
+        assert bad <= 1
+
+
+@pytest.mark.parametrize("dtype,tile", [("c64", 14), ("c128", 13)])
+def test_group_engine_state_dump(dtype, tile):
+    n = 15
+    circ = W.random_small(n, 120, seed=4, measure_all=True)
+    noise = _noise_full(p1=0.3, p2=0.3, gamma=0.3)
+    say(f"case groups dump dtype={dtype}")
+    got = gpu_run(circ, noise, 4, dtype=dtype, seed=1, dump_shot=2, tile_qubits=tile)
+    _, psi = oracle.run(circ, noise, [2], seed=1,
+                        stop_at=len_expanded(circ, noise) - 1, want_state=True)
+    tol = 1e-11 if dtype == "c128" else 5e-5
+    assert np.max(np.abs(got["state"] - psi)) < tol
+
+
+def test_group_engine_branch_mode():
+    n = 15
+    circ = W.random_layered(n, 4, seed=8, mid_measure=(2, (3,)))
+    noise = _noise_full(p1=0.01, p2=0.02, gamma=0.02)
+    shots = 256
+    say("case groups branch mode")
+    got = gpu_run(circ, noise, shots, dtype="c128", mode="branch", seed=6)
+    exp = oracle_memory(circ, noise, shots, seed=6)
+    assert mismatches(got["memory"], exp) == 0
+    assert got["stats"]["branches"] > 0
