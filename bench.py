@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the multi-shot noisy state-vector hot path.
+
+Workload: 20 qubits, 60 layers of random U3 on every qubit + CX on a random
+disjoint pairing; depolarizing noise p=1e-3 after U3 and 1e-2 after CX,
+amplitude damping gamma=5e-3 after U3, 2% symmetric readout error; 100,000
+shots; complex64 storage with FP64 decisions. A step is one wave of
+shots_per_step consecutive shot ids (the default 10 steps x 10,000 shots is
+the whole 100k-shot job), each wave being sv_run_circuit + sv_sample_counts
+through the C ABI. Inputs are seeded and synthetic.
+
+Prints one JSON line (rank 0, N=1). Only one GPU is supported.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VECTOR_PEAK_TF = 157.3    # MI355X published FP32 vector
+FP64_VECTOR_PEAK_TF = 78.6
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "program.h"):
+        with open(os.path.join(ROOT, "paper_2308_03399_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(dtype: str, shots_per_step: int):
+    """HBM bytes per executor launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"exec_kernel_c3_20q_{dtype}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if int(t.get("shots_per_launch", -1)) != shots_per_step:
+        return None
+    return float(t["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(circ, noise, gate_count: int, seed: int):
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    shots = list(range(cores))
+    t0 = time.perf_counter()
+    oracle.run(circ, noise, shots, seed=seed, n_threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": len(shots) * gate_count / dt, "unit": "shots*gates/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"shot ids 0..{len(shots) - 1} of the same workload "
+                      f"(one shot per core, {dt:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--mode", default="batch", choices=["batch", "branch"])
+    ap.add_argument("--shots-per-step", type=int, default=10_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: shots shard across GPUs by "
+              "shot-id range with no exchange, which this build does not "
+              "launch; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2308_03399_amd import Simulator
+
+    w = W.workload("c3_20q")
+    circ, noise, seed = w["circuit"], w["noise"], w["seed"]
+    gates = W.count_gates(circ)
+    B = args.shots_per_step
+    sim = Simulator(circ["n_qubits"], B, dtype=args.dtype, mode=args.mode)
+    stream = sim.stream
+
+    def step(idx):
+        sim_opts_offset = (idx % max(1, (100_000 // B))) * B
+        from paper_2308_03399_amd import sv_batch_set_option
+        sv_batch_set_option(sim.h, "shot_offset", sim_opts_offset)
+        sim.run(circ, noise, seed=seed)
+        counts = sim.counts(capacity=B)
+        return sim.stats(), counts
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        st, counts = step(i)
+        assert sum(counts.values()) == B
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    total_shots = B * args.steps
+    value = total_shots * gates / dt
+    exec_ms = sum(s["exec_ms"] for s in stats)
+    launches = sum(s["exec_launches"] for s in stats)
+    amp_bytes = sum(s["amp_bytes"] for s in stats)
+    flops = sum(s["flops"] for s in stats)
+    gbs = amp_bytes / (exec_ms * 1e-3) / 1e9
+    tfs = flops / (exec_ms * 1e-3) / 1e12
+    alu_peak = FP32_VECTOR_PEAK_TF if args.dtype == "c64" else FP64_VECTOR_PEAK_TF
+    frac_hbm = gbs / HBM_PEAK_GBS
+    frac_alu = tfs / alu_peak
+    traffic = measured_traffic(args.dtype, B)
+    if frac_hbm >= frac_alu:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(frac_hbm, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfs, 3), "peak": alu_peak,
+                "unit": "TFLOP/s", "frac": round(frac_alu, 4)}
+    roof["traffic"] = traffic
+    roof["kernel"] = "svb::exec_kernel"
+    roof["launch_ms"] = round(exec_ms / max(launches, 1), 3)
+    roof["algorithmic_bytes_per_launch"] = int(amp_bytes / max(launches, 1))
+    roof["algorithmic_flops_per_launch"] = int(flops / max(launches, 1))
+    roof["hbm_gbs"] = round(gbs, 1)
+    roof["hbm_frac"] = round(frac_hbm, 4)
+    roof["alu_tflops"] = round(tfs, 3)
+    roof["alu_frac"] = round(frac_alu, 4)
+
+    out = {
+        "metric": "shots×gates/s and achieved HBM GB/s, 20q noisy 100k shots; c64 vs c128",
+        "value": value,
+        "unit": "shots*gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": "c3_20q: 20 qubits x 60 layers random U3 + CX pairing; "
+                        "depolarizing 1e-3 (1q) / 1e-2 (2q), amplitude damping 5e-3, "
+                        "readout 2%; 100,000 shots as waves",
+            "shots_per_step": B,
+            "total_shots": total_shots,
+            "gates_per_shot": gates,
+            "mode": args.mode,
+            "tile_qubits": stats[0]["tile_qubits"],
+            "workers": stats[0]["workers"],
+            "passes_per_shot": round(sum(s["passes"] for s in stats) / total_shots, 2),
+        },
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(circ, noise, gates, seed)
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

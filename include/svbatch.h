@@ -140,7 +140,12 @@ typedef struct {
     uint32_t slots;            /* state slots in the arena                         */
     uint32_t tile_qubits;      /* qubits per LDS tile                              */
     uint32_t static_passes;    /* passes of the static plan                        */
-    uint64_t flops;            /* algorithmic flops of the applied ops             */
+    uint64_t flops;            /* flops of the applied (fused) ops                 */
+    double exec_ms;            /* device time of the executor launches only        */
+    uint32_t exec_launches;    /* executor launches (1 + waiting-list relaunches)   */
+    uint32_t pad;
+    uint64_t groups;           /* register groups executed per sweep, summed       */
+    uint64_t uops;             /* register micro-ops executed per sweep, summed    */
 } sv_stats;
 
 /* Create a handle for n_qubits (1..30) and n_shots (>= 1) in the given
@@ -157,6 +162,10 @@ sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
  *   "dump_shot"    shot id whose state before the final op is kept for
  *                  sv_get_state; -1 disables (default)
  *   "spin_limit_ms" device wait bound of the work queue (default 300000)
+ *   "shot_offset"  global id of shot 0 (default 0): shot i of the handle draws
+ *                  the randoms of global shot shot_offset + i, so a large job
+ *                  can run as consecutive waves, or be split across devices,
+ *                  with the same per-shot results
  * SV_EINVAL on an unknown key or bad value, SV_ESTATE if already attached
  * for keys that change the footprint. */
 sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t value);

@@ -82,7 +82,10 @@ class sv_stats(ctypes.Structure):
                 ("expanded_ops", ctypes.c_uint64),
                 ("gate_count", ctypes.c_uint64), ("workers", ctypes.c_uint32),
                 ("slots", ctypes.c_uint32), ("tile_qubits", ctypes.c_uint32),
-                ("static_passes", ctypes.c_uint32), ("flops", ctypes.c_uint64)]
+                ("static_passes", ctypes.c_uint32), ("flops", ctypes.c_uint64),
+                ("exec_ms", ctypes.c_double), ("exec_launches", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("groups", ctypes.c_uint64),
+                ("uops", ctypes.c_uint64)]
 
     def as_dict(self) -> Dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -160,11 +163,16 @@ def sv_run_circuit(h: int, marshalled, seed: int):
 
 
 def sv_sample_counts(h: int, capacity: int = 0) -> Dict[int, int]:
+    """(key -> count) of the last run. With capacity >= the number of
+    distinct keys (the shot count always is) the histogram is computed once;
+    with capacity 0 the size is queried first."""
     n = ctypes.c_size_t(0)
-    st = lib().sv_sample_counts(h, None, None, 0, ctypes.byref(n))
-    if st not in (0, 1):
-        _check(st)
-    cap = max(int(n.value), 1)
+    cap = int(capacity)
+    if cap <= 0:
+        st = lib().sv_sample_counts(h, None, None, 0, ctypes.byref(n))
+        if st not in (0, 1):
+            _check(st)
+        cap = max(int(n.value), 1)
     keys = np.zeros(cap, dtype=np.uint64)
     counts = np.zeros(cap, dtype=np.uint64)
     _check(lib().sv_sample_counts(h, keys.ctypes.data, counts.ctypes.data, cap,
@@ -293,8 +301,8 @@ class Simulator:
         with self.torch.cuda.device(self.device):
             sv_run_circuit(self.h, m, seed)
 
-    def counts(self) -> Dict[int, int]:
-        return sv_sample_counts(self.h)
+    def counts(self, capacity: int = 0) -> Dict[int, int]:
+        return sv_sample_counts(self.h, capacity or self.n_shots)
 
     def memory(self) -> np.ndarray:
         return sv_get_memory(self.h, self.n_shots)

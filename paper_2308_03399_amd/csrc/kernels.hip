@@ -222,6 +222,20 @@ __device__ __forceinline__ UOp get_uop(const lds<UOp> *p)
     return u;
 }
 
+// Byte offset of the per-workgroup state in dynamic LDS (after the tile,
+// the offset table, the decisions and the micro-op area).
+__device__ __forceinline__ uint32_t svb_side_bytes_dev(int tile_q, int amp_bytes, int resident)
+{
+    const uint32_t tile = (1u << tile_q) * amp_bytes;
+    const uint32_t hi = resident ? 16u : (1u << (tile_q - kCoalesceQ)) * 4u;
+    const uint32_t dec = kMaxPassOps * 2;
+    const uint32_t fuse = kMaxPassGroups * 16 + kMaxPassUops * 8 + kPassMatBytes + 8 * 8 * 8;
+    const uint32_t cnt = 16u * kWG * 4u;
+    const bool cnt_in_tile = !resident && tile >= cnt;
+    const uint32_t ua = (!cnt_in_tile && cnt > fuse) ? cnt : fuse;
+    return (tile + hi + dec + ua + 15u) / 16u * 16u;
+}
+
 template <class R>
 struct Ctx {
     using A = typename V2<R>::T;
@@ -229,8 +243,10 @@ struct Ctx {
     lds<WgShared> &S;
     lds<A> *L;         // LDS tile (2^k amplitudes, swizzled positions)
     lds<uint32_t> *hi_off;  // LDS: global offset of local index bits >= 4
-    lds<int> *dec;     // LDS: decided outcome of each op of the pass
-    lds<int> *cnt;     // LDS: 16 x kWG outcome counters (splits), aliases the uop area
+    lds<int16_t> *dec; // LDS: decided outcome of each op of the pass
+    lds<int> *cnt;     // LDS: 16 x kWG outcome counters (splits); aliases the tile
+                       // of a streamed state (free between sweeps)
+    lds<unsigned char> *scr;  // LDS: scratch (aliases the micro-op area)
     lds<UGroup> *ug;   // LDS: register groups of the pass
     lds<UOp> *uops;    // LDS: micro-ops of the pass
     lds<R> *mats;      // LDS: fused matrices of the pass (8 reals each)
@@ -593,21 +609,23 @@ __device__ void run_group(Ctx<R> &c, const GroupInfo &gi, int first, int count)
 {
     using A = typename V2<R>::T;
     constexpr int RB = NR == 64 ? 6 : NR == 32 ? 5 : NR == 16 ? 4 : 3;
+    constexpr int SH = sizeof(A) == 8 ? 3 : 4;
     uint32_t base = 0;
     for (int i = 0; i < c.k - RB; ++i) base |= ((uint32_t)(c.tid >> i) & 1u) << gi.cpos[i];
-    const uint32_t pb = c.at(base);
-    uint32_t pe[RB];
+    // byte position of register i = (thread part) ^ (uniform part); the
+    // swizzle is linear over disjoint bits, so the parts combine by XOR
+    const uint32_t pb8 = c.at(base) << SH;
+    uint32_t pe8[RB];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) pe[j] = c.at(1u << gi.gpos[j]);
+    for (int j = 0; j < RB; ++j) pe8[j] = __builtin_amdgcn_readfirstlane(c.at(1u << gi.gpos[j]) << SH);
+    uint32_t K[NR];
+    K[0] = 0;
+#pragma unroll
+    for (int i = 1; i < NR; ++i) K[i] = K[i & (i - 1)] ^ pe8[__builtin_ctz(i)];
+    // the tile starts at LDS address 0, so pb8 ^ K[i] is the address itself
     A v[NR];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        uint32_t p = pb;
-#pragma unroll
-        for (int j = 0; j < RB; ++j)
-            if ((i >> j) & 1) p ^= pe[j];
-        v[i] = c.L[p];
-    }
+    for (int i = 0; i < NR; ++i) v[i] = *(const lds<A> *)(size_t)(pb8 ^ K[i]);
     for (int q = 0; q < count; ++q) {
         const UOp u = get_uop(c.uops + first + q);
         if (u.kind == UK_MAT1 || u.kind == UK_DIAG1) {
@@ -619,16 +637,85 @@ __device__ void run_group(Ctx<R> &c, const GroupInfo &gi, int first, int count)
             d_two<A, NR>(v, u.kind, u.j0, u.j1);
         }
     }
+    // recompute the addresses rather than keep NR of them live
+    uint32_t pw = pb8;
+    asm volatile("" : "+v"(pw));
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        uint32_t p = pb;
-#pragma unroll
-        for (int j = 0; j < RB; ++j)
-            if ((i >> j) & 1) p ^= pe[j];
-        c.L[p] = v[i];
-    }
+    for (int i = 0; i < NR; ++i) *(lds<A> *)(size_t)(pw ^ K[i]) = v[i];
     __syncthreads();
 }
+
+// Per-pass chunk offsets of a thread for streamed tile copies: global byte
+// offset from the tile's base (uniform) and LDS byte position, so a copy
+// is a scalar-base load/store with a precomputed vector offset.
+template <class R, int NR>
+struct TileIO {
+    // Chunk u of thread t holds tile index l = (u*kWG + t)*V. Both the
+    // global offset (hi_off is a bit deposit) and the LDS position (the
+    // swizzle is an XOR of bit fields) split into a per-thread part and a
+    // per-u part that is the same for every thread of the workgroup.
+    using A = typename V2<R>::T;
+    static constexpr int V = 16 / sizeof(A);
+    static constexpr int NC = NR / V;
+    uint32_t gt;   // per-thread global byte offset
+    uint32_t pt;   // per-thread LDS byte position
+
+    __device__ void setup(Ctx<R> &c)
+    {
+        const uint32_t l = (uint32_t)c.tid * V;
+        gt = (c.hi_off[l >> 4] + (l & 15u)) * (uint32_t)sizeof(A);
+        pt = c.at(l) * (uint32_t)sizeof(A);
+    }
+    __device__ __forceinline__ uint32_t gu(Ctx<R> &c, int u) const
+    {
+        return __builtin_amdgcn_readfirstlane(c.hi_off[(uint32_t)(u * kWG * V) >> 4] *
+                                              (uint32_t)sizeof(A));
+    }
+    __device__ __forceinline__ uint32_t pu(Ctx<R> &c, int u) const
+    {
+        return __builtin_amdgcn_readfirstlane(c.at((uint32_t)(u * kWG * V)) * (uint32_t)sizeof(A));
+    }
+
+    __device__ void load(Ctx<R> &c, const gbl<A> *Gt, uint64_t base, bool fresh)
+    {
+        if (fresh) {
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+                const uint64_t g = base + (gt + gu(c, u)) / sizeof(A);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    A z;
+                    z.x = (g + e == 0) ? (R)1 : (R)0;
+                    z.y = 0;
+                    *(lds<A> *)(size_t)((pt ^ pu(c, u)) + e * sizeof(A)) = z;
+                }
+            }
+        } else {
+            const gbl<unsigned char> *Gb = (const gbl<unsigned char> *)(Gt + base);
+            constexpr int BATCH = NC < 16 ? NC : 16;
+#pragma unroll
+            for (int u0 = 0; u0 < NC; u0 += BATCH) {
+                u32x4 x[BATCH];
+#pragma unroll
+                for (int u = 0; u < BATCH; ++u)
+                    x[u] = *(const gbl<u32x4> *)(Gb + gu(c, u0 + u) + gt);
+#pragma unroll
+                for (int u = 0; u < BATCH; ++u)
+                    *(lds<u32x4> *)(size_t)(pt ^ pu(c, u0 + u)) = x[u];
+            }
+        }
+        __syncthreads();
+    }
+
+    __device__ void store(Ctx<R> &c, gbl<A> *Gt, uint64_t base)
+    {
+        gbl<unsigned char> *Gb = (gbl<unsigned char> *)(Gt + base);
+#pragma unroll
+        for (int u = 0; u < NC; ++u)
+            *(gbl<u32x4> *)(Gb + gu(c, u) + gt) = *(const lds<u32x4> *)(size_t)(pt ^ pu(c, u));
+        __syncthreads();
+    }
+};
 
 // ---- plan-time fusion (thread 0): per register bit a pending FP64 2x2
 // matrix collects consecutive one-qubit factors (gate, drawn Pauli, chosen
@@ -720,7 +807,8 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
         int o = a;
         for (; o < b; ++o) {
             // room for this op (<= 3 micro-ops) and the group's final flush (<= 8)
-            if (nu + 11 > kMaxPassUops || nm + 11 > kMaxPassMats) { cut = true; break; }
+            constexpr int kMats = kPassMatBytes / (8 * (int)sizeof(R));
+            if (nu + 11 > kMaxPassUops || nm + 11 > kMats) { cut = true; break; }
             const DevOp &op = P.ops[o];
             const int d = c.dec[o - S.start];
             const double sc = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
@@ -777,6 +865,8 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
     if (cut) S.stop = STOP_NONE;
     S.n_ug = ng;
     S.pass_flops = flops;
+    S.st[ST_GROUPS] += ng;
+    S.st[ST_UOPS] += nu;
 }
 
 // ----------------------------------------------------------- reductions
@@ -1079,7 +1169,7 @@ __device__ __noinline__ void record_bits(const ExecParams &P, const DevOp &op, u
     for (int t = 0; t < op.nq; ++t) {
         uint64_t bit = (o >> t) & 1u;
         const double pf = bit ? P.ro10 : P.ro01;
-        if (pf > 0 && philox_u01(P.seed, shot, op.r, 1u + t) < pf) bit ^= 1u;
+        if (pf > 0 && philox_u01(P.seed, P.shot_base + shot, op.r, 1u + t) < pf) bit ^= 1u;
         m = (m & ~(1ull << op.c[t])) | (bit << op.c[t]);
     }
     P.memory[shot] = m;
@@ -1089,7 +1179,7 @@ __device__ __noinline__ void record_bits(const ExecParams &P, const DevOp &op, u
 __device__ __forceinline__ int outcome_of(const ExecParams &P, const lds<WgShared> &S,
                                           const DevOp &op, uint64_t shot)
 {
-    const double u = philox_u01(P.seed, shot, op.r, 0);
+    const double u = philox_u01(P.seed, P.shot_base + shot, op.r, 0);
     if (op.kind == DK_PAULI) return pauli_pick(P, P.rules[op.rule], u);
     return red_pick(S, red_count(P, op), u);
 }
@@ -1273,7 +1363,7 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
         if (m == 1) {
             // every thread evaluates the single shot's draw (no barrier)
             const uint64_t shot = (uint64_t)P.shot_perm[S.lo];
-            const double u = philox_u01(P.seed, shot, op.r, 0);
+            const double u = philox_u01(P.seed, P.shot_base + shot, op.r, 0);
             if (op.kind == DK_PAULI) {
                 if (tid == 0) c.dec[j - start] = pauli_pick(P, ru, u);
                 ++j;
@@ -1294,7 +1384,7 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
         int lmin = 1 << 30, lmax = -1, high = 0;
         for (int i = S.lo + tid; i < S.hi; i += kWG) {
             const uint64_t shot = (uint64_t)P.shot_perm[i];
-            const double u = philox_u01(P.seed, shot, op.r, 0);
+            const double u = philox_u01(P.seed, P.shot_base + shot, op.r, 0);
             if (op.kind == DK_PAULI) {
                 const int o = pauli_pick(P, ru, u);
                 lmin = min(lmin, o);
@@ -1406,18 +1496,33 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
         build_hi_off(c, pi, k);
         gbl<A> *G = slot_ptr<R>(P, S.slot);
         const bool fresh = S.fresh != 0;
-        for (uint32_t t = 0; t < c.n_tiles; ++t) {
-            const uint64_t base = tile_base<R>(pi, n, k, t);
-            load_tile(c, G, base, fresh);
-            if (grp) run_groups<R, NR>(c, flops);
-            else apply_range(c, flops);
-            if (want_reduce) {
-                reduce_tile(c, rop, acc);
+        if constexpr (NR > 0) {
+            if (P.use_groups) {
+                TileIO<R, NR> io;
+                io.setup(c);
+                for (uint32_t t = 0; t < c.n_tiles; ++t) {
+                    const uint64_t base = tile_base<R>(pi, n, k, t);
+                    io.load(c, G, base, fresh);
+                    if (grp) run_groups<R, NR>(c, flops);
+                    if (want_reduce) reduce_tile(c, rop, acc);
+                    if (has_ops) io.store(c, G, base);
+                }
             }
-            if (has_ops) store_tile(c, G, base);
+        }
+        if (!(NR > 0 && P.use_groups)) {
+            for (uint32_t t = 0; t < c.n_tiles; ++t) {
+                const uint64_t base = tile_base<R>(pi, n, k, t);
+                load_tile(c, G, base, fresh);
+                if (grp) run_groups<R, NR>(c, flops);
+                else apply_range(c, flops);
+                if (want_reduce) {
+                    reduce_tile(c, rop, acc);
+                }
+                if (has_ops) store_tile(c, G, base);
+            }
         }
         c.swm = 0;
-        if (grp) flops = S.pass_flops;
+        if (grp) flops = S.pass_flops * c.n_tiles;
         if (c.tid == 0) {
             const uint64_t sb = (1ull << n) * sizeof(A);
             S.st[ST_PASSES] += 1;
@@ -1518,7 +1623,7 @@ __device__ __noinline__ void terminal_sample(Ctx<R> &c)
             }
         }
         // segment offsets (sequential over segments, fixed order)
-        lds<double> *off = (lds<double> *)c.cnt;   // kWG doubles
+        lds<double> *off = (lds<double> *)c.scr;   // kWG doubles
         if (active) off[tid] = run; else if (tid < kWG) off[tid] = 0;
         __syncthreads();
         if (tid == 0) {
@@ -1567,7 +1672,7 @@ __device__ __noinline__ void terminal_sample(Ctx<R> &c)
     // tile of each shot -> shot_tmp[i]
     for (int i = S.lo + tid; i < S.hi; i += kWG) {
         const uint64_t shot = (uint64_t)P.shot_perm[i];
-        const double x = philox_u01(P.seed, shot, op.r, 0) * N;
+        const double x = philox_u01(P.seed, P.shot_base + shot, op.r, 0) * N;
         int t = -1;
         uint32_t lo = 0, hi = c.n_tiles;  // first t with x < tsums[t]
         while (lo < hi) {
@@ -1605,7 +1710,7 @@ __device__ __noinline__ void terminal_sample(Ctx<R> &c)
         for (int i = S.lo + tid; i < S.hi; i += kWG) {
             if (P.shot_tmp[i] != (int)t) continue;
             const uint64_t shot = (uint64_t)P.shot_perm[i];
-            const double x = philox_u01(P.seed, shot, op.r, 0) * N;
+            const double x = philox_u01(P.seed, P.shot_base + shot, op.r, 0) * N;
             uint32_t lo = 0, hi = c.tsize;  // first e with x < excl + D[e]
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
@@ -1621,7 +1726,7 @@ __device__ __noinline__ void terminal_sample(Ctx<R> &c)
             for (int q = 0; q < n; ++q) {
                 uint64_t bit = (idx >> q) & 1u;
                 const double pf = bit ? P.ro10 : P.ro01;
-                if (pf > 0 && philox_u01(P.seed, shot, op.r, 1u + q) < pf) bit ^= 1u;
+                if (pf > 0 && philox_u01(P.seed, P.shot_base + shot, op.r, 1u + q) < pf) bit ^= 1u;
                 mm = (mm & ~(1ull << op.c[q])) | (bit << op.c[q]);
             }
             P.memory[shot] = mm;
@@ -1693,8 +1798,10 @@ __global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
 {
     using A = typename V2<R>::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ WgShared S_;
-    lds<WgShared> &S = *(lds<WgShared> *)&S_;
+    // no static LDS: the tile starts at LDS address 0 and the per-workgroup
+    // state sits at the end of the dynamic allocation
+    lds<unsigned char> *sm0 = (lds<unsigned char> *)smem;
+    lds<WgShared> &S = *(lds<WgShared> *)(sm0 + svb_side_bytes_dev(P.tile_q, (int)sizeof(A), P.resident));
     const int tid = threadIdx.x;
     const int n = P.n_qubits, k = P.tile_q;
     Ctx<R> c{P, S};
@@ -1703,17 +1810,20 @@ __global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
     c.swm = 0;
     c.tsize = 1u << k;
     c.n_tiles = P.resident ? 1u : (1u << (n - k));
-    lds<unsigned char> *sm = (lds<unsigned char> *)smem;
+    lds<unsigned char> *sm = sm0;
     c.L = (lds<A> *)sm;
     c.hi_off = (lds<uint32_t> *)(sm + (size_t)c.tsize * sizeof(A));
     const uint32_t n_hi = P.resident ? 4u : (1u << (k - kCoalesceQ));
-    c.dec = (lds<int> *)(c.hi_off + n_hi);
+    c.dec = (lds<int16_t> *)(c.hi_off + n_hi);
     lds<unsigned char> *uarea = (lds<unsigned char> *)(c.dec + kMaxPassOps);
-    c.cnt = (lds<int> *)uarea;
+    c.scr = uarea;
+    // split counters live in the tile when it is streamed and large enough
+    const bool cnt_in_tile = !P.resident && (size_t)c.tsize * sizeof(A) >= 16u * kWG * 4u;
+    c.cnt = cnt_in_tile ? (lds<int> *)sm : (lds<int> *)uarea;
     c.ug = (lds<UGroup> *)uarea;
     c.uops = (lds<UOp> *)(uarea + kMaxPassGroups * sizeof(UGroup));
     c.mats = (lds<R> *)((lds<unsigned char> *)c.uops + kMaxPassUops * sizeof(UOp));
-    c.pend = (lds<double> *)((lds<unsigned char> *)c.mats + kMaxPassMats * 8 * sizeof(R));
+    c.pend = (lds<double> *)((lds<unsigned char> *)c.mats + kPassMatBytes);
     if (tid < ST_COUNT) S.st[tid] = 0;
     __syncthreads();
 
@@ -1909,21 +2019,22 @@ __global__ void restart_kernel(ExecParams P, int n_wait)
 }  // namespace svb
 
 // ------------------------------------------------------------ launchers
-static size_t uarea_bytes(int amp_bytes)
+static size_t uarea_bytes(int cnt_in_tile)
 {
-    const size_t real = amp_bytes / 2;
     const size_t fuse = svb::kMaxPassGroups * sizeof(svb::UGroup) + svb::kMaxPassUops * sizeof(svb::UOp) +
-                        svb::kMaxPassMats * 8 * real + 8 * 8 * sizeof(double);
-    const size_t cnt = 16 * svb::kWG * 4;
-    return fuse > cnt ? fuse : cnt;
+                        svb::kPassMatBytes + 8 * 8 * sizeof(double);
+    const size_t cnt = 16 * svb::kWG * 4;  // split counters, unless they fit in the tile
+    return (!cnt_in_tile && cnt > fuse) ? cnt : fuse;
 }
 
 extern "C" size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident)
 {
     const size_t tile = ((size_t)1 << tile_q) * amp_bytes;
     const size_t hi = resident ? 4 * 4 : ((size_t)1 << (tile_q - svb::kCoalesceQ)) * 4;
-    const size_t dec = svb::kMaxPassOps * 4;
-    return tile + hi + dec + uarea_bytes(amp_bytes);
+    const size_t dec = svb::kMaxPassOps * 2;
+    const int cnt_in_tile = !resident && tile >= 16u * svb::kWG * 4u;
+    const size_t side = (tile + hi + dec + uarea_bytes(cnt_in_tile) + 15) / 16 * 16;
+    return side + sizeof(svb::WgShared);
 }
 
 extern "C" {

@@ -9,8 +9,8 @@ namespace svb {
 constexpr int kWG = 256;             // threads per executor workgroup
 constexpr int kMaxPassOps = 512;     // ops applied in one tile sweep
 constexpr int kMaxPassGroups = 64;   // register groups in one sweep
-constexpr int kMaxPassUops = 512;    // register micro-ops in one sweep
-constexpr int kMaxPassMats = 256;    // fused 2x2 matrices in one sweep
+constexpr int kMaxPassUops = 384;    // register micro-ops in one sweep
+constexpr int kPassMatBytes = 6144;  // LDS bytes for the fused 2x2 matrices of one sweep
 constexpr int kMaxKraus = 8;         // matrices per Kraus channel
 constexpr int kMaxMeasQ = 4;         // qubits of a non-terminal measure
 constexpr int kMaxRed = 1 + 16;      // norm + up to 16 outcome sums
@@ -100,7 +100,7 @@ struct BranchRec {
 
 enum CtlStat {
     ST_PASSES = 0, ST_BYTES, ST_REDUCTIONS, ST_BRANCHES, ST_WAITING,
-    ST_FLOPS, ST_SPLITS, ST_COUNT
+    ST_FLOPS, ST_SPLITS, ST_GROUPS, ST_UOPS, ST_COUNT
 };
 
 struct Control {
@@ -141,6 +141,7 @@ struct ExecParams {
     int32_t *waiting;
     void *dump;              // normalised state of dump_shot (complex)
     uint64_t seed;
+    uint64_t shot_base;      // global id of local shot 0 (Philox counter)
     int64_t n_shots;
     int64_t dump_shot;
     unsigned long long spin_limit;   // wall-clock ticks

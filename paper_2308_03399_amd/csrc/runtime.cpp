@@ -73,6 +73,7 @@ struct sv_batch {
     int64_t program_bytes = 8 << 20;
     int64_t dump_shot = -1;
     int64_t spin_ms = 300000;
+    int64_t shot_offset = 0;
     // derived
     int tile_q = 0, resident = 0, workers = 0, slots = 0;
     int use_groups = 0, reg_bits = 0;  // register-group engine, log2(amps per thread)
@@ -92,7 +93,7 @@ struct sv_batch {
     bool have_results = false;
     bool have_dump = false;
     sv_stats stats{};
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
 };
 
 static int amp_bytes(const sv_batch *b) { return b->dtype == SV_C128 ? 16 : 8; }
@@ -113,10 +114,14 @@ static sv_status derive(sv_batch *b)
                                                      : prop.sharedMemPerBlock;
     if (prop.maxSharedMemoryPerMultiProcessor > 0)
         lds_cap = std::min(lds_cap, (size_t)prop.maxSharedMemoryPerMultiProcessor);
-    const size_t static_lds = 4096;  // executor's static shared state, rounded up
+    const size_t static_lds = 0;  // the executor keeps all its LDS state in the dynamic block
     int kmax = b->dtype == SV_C128 ? 13 : kMaxTileQ;
     while (kmax > 6 && svb_exec_lds_bytes(kmax, amp_bytes(b), 0) + static_lds > lds_cap) --kmax;
-    int k = b->opt_tile > 0 ? (int)b->opt_tile : kmax;
+    // default: the largest tile of which two workgroups fit on a compute unit
+    // (one streams its tile while the other computes)
+    int kdef = kmax;
+    while (kdef > 6 && 2 * (svb_exec_lds_bytes(kdef, amp_bytes(b), 0) + static_lds) > lds_cap) --kdef;
+    int k = b->opt_tile > 0 ? (int)b->opt_tile : kdef;
     if (k > kmax) k = kmax;
     if (b->n <= k) {
         b->resident = 1;
@@ -730,6 +735,9 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
     } else if (k == "engine") {
         if (v < 0 || v > 1) return fail(SV_EINVAL, "engine %lld (0 automatic, 1 LDS sweeps)", (long long)v);
         b->opt_engine = v;
+    } else if (k == "shot_offset") {
+        if (v < 0) return fail(SV_EINVAL, "shot_offset %lld", (long long)v);
+        b->shot_offset = v;
     } else if (k == "spin_limit_ms") {
         if (v < 1) return fail(SV_EINVAL, "spin_limit_ms %lld", (long long)v);
         b->spin_ms = v;
@@ -767,6 +775,8 @@ sv_status sv_batch_attach(sv_batch *b, void *arena, uint64_t bytes, void *stream
     if (!b->ev0) {
         HIPCHK(hipEventCreate(&b->ev0));
         HIPCHK(hipEventCreate(&b->ev1));
+        HIPCHK(hipEventCreate(&b->ev2));
+        HIPCHK(hipEventCreate(&b->ev3));
     }
     b->attached = true;
     b->have_results = false;
@@ -910,6 +920,7 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     P.waiting = (int32_t *)(A + L.waiting);
     P.dump = b->dump_shot >= 0 ? (void *)(A + L.dump) : nullptr;
     P.seed = seed;
+    P.shot_base = (uint64_t)b->shot_offset;
     P.n_shots = b->shots;
     P.dump_shot = b->dump_shot;
     P.spin_limit = (unsigned long long)b->spin_ms * (unsigned long long)b->wallclock_khz;
@@ -933,11 +944,19 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     uint64_t restarts = 0;
     HIPCHK(hipEventRecord(b->ev0, b->stream));
     HIPCHK(svb_launch_init(&P, 0, (int)b->shots, root_slot, n_free, b->stream));
+    double exec_ms = 0;
+    uint32_t exec_launches = 0;
     for (;;) {
+        HIPCHK(hipEventRecord(b->ev2, b->stream));
         HIPCHK(svb_launch_exec(&P, b->dtype == SV_C128, b->reg_bits, b->workers, b->stream));
+        HIPCHK(hipEventRecord(b->ev3, b->stream));
         Control ctl;
         HIPCHK(hipMemcpyAsync(&ctl, P.ctl, sizeof ctl, hipMemcpyDeviceToHost, b->stream));
         HIPCHK(hipStreamSynchronize(b->stream));
+        float lms = 0;
+        HIPCHK(hipEventElapsedTime(&lms, b->ev2, b->ev3));
+        exec_ms += lms;
+        ++exec_launches;
         if (ctl.error) return fail(SV_EDEVICE, "device executor failed (flags 0x%x)", ctl.error);
         for (int i = 0; i < ST_COUNT; ++i) acc[i] += ctl.stat[i];
         if (ctl.wait_count == 0) break;
@@ -966,6 +985,10 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     st.tile_qubits = (uint32_t)b->tile_q;
     st.static_passes = (uint32_t)passes.size();
     st.flops = acc[ST_FLOPS];
+    st.exec_ms = exec_ms;
+    st.groups = acc[ST_GROUPS];
+    st.uops = acc[ST_UOPS];
+    st.exec_launches = exec_launches;
     b->have_results = true;
     b->have_dump = b->dump_shot >= 0;
     return SV_OK;
@@ -1031,6 +1054,8 @@ sv_status sv_batch_destroy(sv_batch *b)
     if (!b) return SV_OK;
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->ev2) (void)hipEventDestroy(b->ev2);
+    if (b->ev3) (void)hipEventDestroy(b->ev3);
     delete b;
     return SV_OK;
 }

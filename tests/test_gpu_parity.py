@@ -165,3 +165,15 @@ def test_group_engine_branch_mode():
     exp = oracle_memory(circ, noise, shots, seed=6)
     assert mismatches(got["memory"], exp) == 0
     assert got["stats"]["branches"] > 0
+
+
+def test_shot_offset_waves_equal_one_job():
+    # a job run as two waves (shot_offset) equals the same shots in one run
+    circ = W.random_layered(15, 4, seed=2)
+    noise = _noise_full(p1=0.02, p2=0.04, gamma=0.03)
+    say("case shot_offset waves")
+    exp = oracle_memory(circ, noise, 300, seed=9)
+    a = gpu_run(circ, noise, 120, dtype="c128", seed=9)
+    b = gpu_run(circ, noise, 180, dtype="c128", seed=9, shot_offset=120)
+    assert mismatches(a["memory"], exp[:120]) == 0
+    assert mismatches(b["memory"], exp[120:]) == 0
