@@ -210,14 +210,31 @@ __device__ __forceinline__ void put_uop(lds<UOp> *p, const UOp &u)
     p->pad2 = 0;
 }
 
+// Micro-ops are the same for every thread: read them as scalars so that
+// their dispatch compiles to scalar branches, not exec-masked compares.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
+}
+__device__ __forceinline__ double uni(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint64_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
 __device__ __forceinline__ UOp get_uop(const lds<UOp> *p)
 {
+    const uint64_t w = *(const lds<uint64_t> *)p;
+    const uint32_t lo = uni((uint32_t)w), hi = uni((uint32_t)(w >> 32));
     UOp u;
-    u.kind = p->kind;
-    u.j0 = p->j0;
-    u.j1 = p->j1;
+    u.kind = (uint8_t)lo;
+    u.j0 = (uint8_t)(lo >> 8);
+    u.j1 = (uint8_t)(lo >> 16);
     u.pad = 0;
-    u.mat = p->mat;
+    u.mat = (uint16_t)hi;
     u.pad2 = 0;
     return u;
 }
@@ -631,7 +648,7 @@ __device__ void run_group(Ctx<R> &c, const GroupInfo &gi, int first, int count)
         if (u.kind == UK_MAT1 || u.kind == UK_DIAG1) {
             R m[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) m[e] = c.mats[u.mat * 8 + e];
+            for (int e = 0; e < 8; ++e) m[e] = uni(c.mats[u.mat * 8 + e]);
             d_mat1<A, R, NR>(v, u.j0, m, u.kind == UK_DIAG1);
         } else {
             d_two<A, NR>(v, u.kind, u.j0, u.j1);
@@ -1454,13 +1471,14 @@ __device__ void run_groups(Ctx<R> &c, uint64_t &flops)
 {
     const ExecParams &P = c.P;
     lds<WgShared> &S = c.S;
-    for (int u = 0; u < S.n_ug; ++u) {
+    const int n_ug = (int)uni((uint32_t)S.n_ug);
+    for (int u = 0; u < n_ug; ++u) {
         const lds<UGroup> &gl = c.ug[u];
         UGroup g;
-        g.gidx = gl.gidx;
-        g.a = gl.a;
-        g.b = gl.b;
-        g.fallback = gl.fallback;
+        g.gidx = (int32_t)uni((uint32_t)gl.gidx);
+        g.a = (int32_t)uni((uint32_t)gl.a);
+        g.b = (int32_t)uni((uint32_t)gl.b);
+        g.fallback = (int32_t)uni((uint32_t)gl.fallback);
         if (g.fallback) {
             for (int o = g.a; o < g.b; ++o) {
                 const double s = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;

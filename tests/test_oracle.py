@@ -190,13 +190,17 @@ def test_reset_then_measure_is_zero():
 
 
 def test_state_stays_normalised_through_kraus_and_measure():
+    # the norm is checked after every expanded op (a later measurement would
+    # renormalise a wrongly scaled Kraus result)
     noise = W.noise_model([W.rule(["u3"], W.amplitude_damping_kraus(0.2)),
                            W.rule(["cx"], W.depolarizing_pauli(0.3, 2))])
-    circ = W.random_layered(4, 6, seed=2, measure_all=False,
-                            mid_measure=(2, (0, 3)))
-    for shot in range(20):
-        psi = _state(circ, noise, shot=shot)
-        assert abs(np.vdot(psi, psi).real - 1) < 1e-12
+    circ = W.random_layered(3, 3, seed=2, measure_all=False,
+                            mid_measure=(2, (0, 2)))
+    n_x = len(dm.expand(circ, noise))
+    for shot in range(6):
+        for stop in range(1, n_x + 1):
+            psi = _state(circ, noise, shot=shot, stop_at=stop)
+            assert abs(np.vdot(psi, psi).real - 1) < 1e-12, (shot, stop)
 
 
 # --------------------------------------------------------------------------
