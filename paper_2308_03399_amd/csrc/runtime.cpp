@@ -1049,6 +1049,59 @@ sv_status sv_get_stats(sv_batch *b, sv_stats *out)
     return SV_OK;
 }
 
+// Host-only introspection of the execution plan (tests): device order of the
+// expanded ops (as expanded-list indices), their pass and group, each pass's
+// tile-qubit mask and each group's register-qubit count (-1: LDS group).
+sv_status svb_debug_plan(int n_qubits, int tile_q, int reg_bits, const sv_op *ops, size_t n_ops,
+                         const sv_noise_model *nm, int32_t *order, int32_t *op_pass,
+                         int32_t *op_group, uint32_t *pass_mask, int32_t *group_width,
+                         size_t cap, size_t *n_out, size_t *n_passes, size_t *n_groups)
+{
+    sv_batch tmp;
+    tmp.n = n_qubits;
+    tmp.shots = 1;
+    std::vector<Rule> rules;
+    std::vector<XOp> xo;
+    double ro01, ro10;
+    uint64_t gc;
+    sv_status s = validate_and_expand(&tmp, ops, n_ops, nm, rules, xo, ro01, ro10, gc);
+    if (s != SV_OK) return s;
+    bool terminal = false;
+    if (!xo.empty()) {
+        const XOp &last = xo.back();
+        if (last.kind == SV_OP_MEASURE && (int)last.q.size() == n_qubits) {
+            terminal = true;
+            for (int t = 0; t < n_qubits; ++t) terminal = terminal && last.q[t] == t;
+        }
+    }
+    const bool resident = n_qubits <= tile_q;
+    Plan plan;
+    plan_program(n_qubits, resident ? n_qubits : tile_q, reg_bits, resident, reg_bits > 0, 62u, xo,
+                 rules, terminal, plan);
+    *n_out = plan.order.size();
+    *n_passes = plan.passes.size();
+    *n_groups = plan.groups.size();
+    if (plan.order.size() > cap || plan.passes.size() > cap || plan.groups.size() > cap)
+        return fail(SV_EINVAL, "capacity %zu too small", cap);
+    for (size_t i = 0; i < plan.order.size(); ++i) {
+        order[i] = (int32_t)plan.order[i];
+        op_pass[i] = (int32_t)plan.op_pass[i];
+        op_group[i] = (int32_t)plan.op_group[i];
+    }
+    for (size_t p = 0; p < plan.passes.size(); ++p) pass_mask[p] = plan.passes[p].tmask;
+    for (size_t g = 0; g < plan.groups.size(); ++g) {
+        if (plan.groups[g].fallback) {
+            group_width[g] = -1;
+        } else {
+            uint32_t m = 0;
+            for (uint32_t j = plan.groups[g].first_op; j < plan.groups[g].end_op; ++j)
+                m |= qmask_of(xo[plan.order[j]]);
+            group_width[g] = __builtin_popcount(m);
+        }
+    }
+    return SV_OK;
+}
+
 sv_status sv_batch_destroy(sv_batch *b)
 {
     if (!b) return SV_OK;

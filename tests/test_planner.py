@@ -1,0 +1,96 @@
+"""Host-side execution planner (no GPU): the device order is a permutation
+of the expanded op list that keeps the order of ops sharing a qubit and the
+relative order of state-dependent random ops (Kraus, measure, reset); every
+pass fits its tile and every register group its register bits."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2308_03399_amd as S
+import workloads as W
+from oracle import dm
+
+
+def _plan(circ, noise, tile_q, reg_bits):
+    L = S.lib()
+    f = L.svb_debug_plan
+    P = ctypes.c_void_p
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(S.sv_op),
+                  ctypes.c_size_t, ctypes.POINTER(S.sv_noise_model), P, P, P, P, P,
+                  ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t),
+                  ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    m = S.marshal(circ, noise)
+    cap = 200_000
+    order = np.zeros(cap, np.int32)
+    opass = np.zeros(cap, np.int32)
+    ogrp = np.zeros(cap, np.int32)
+    pmask = np.zeros(cap, np.uint32)
+    gw = np.zeros(cap, np.int32)
+    n = ctypes.c_size_t()
+    np_ = ctypes.c_size_t()
+    ng = ctypes.c_size_t()
+    st = f(circ["n_qubits"], tile_q, reg_bits, m["ops"], m["n_ops"], m["nm"],
+           order.ctypes.data, opass.ctypes.data, ogrp.ctypes.data, pmask.ctypes.data,
+           gw.ctypes.data, cap, ctypes.byref(n), ctypes.byref(np_), ctypes.byref(ng))
+    assert st == 0, S.sv_last_error()
+    return (order[:n.value], opass[:n.value], ogrp[:n.value], pmask[:np_.value],
+            gw[:ng.value])
+
+
+def _is_ordered_random(x):
+    return (x["kind"] == "channel" and x["rule"]["type"] == "kraus") or \
+        x["kind"] in ("measure", "reset", "measure_reset")
+
+
+@pytest.mark.parametrize("case", ["c3", "c2", "small"])
+@pytest.mark.parametrize("tile_q,reg_bits", [(13, 5), (14, 6), (12, 4), (8, 0)])
+def test_plan_respects_dependencies(case, tile_q, reg_bits):
+    if case == "c3":
+        w = W.workload("c3_20q")
+        circ = dict(w["circuit"], ops=w["circuit"]["ops"][:900] + w["circuit"]["ops"][-1:])
+        noise = w["noise"]
+    elif case == "c2":
+        w = W.workload("c2_16q")
+        circ, noise = w["circuit"], w["noise"]
+    else:
+        circ = W.random_small(16, 300, seed=5, n_mid=6)
+        noise = W.noise_model([W.rule(["u3", "h"], W.amplitude_damping_kraus(0.1)),
+                               W.rule(["cx", "cz"], W.depolarizing_pauli(0.1, 2))])
+    xo = dm.expand(circ, noise)
+    order, opass, ogrp, pmask, gw = _plan(circ, noise, tile_q, reg_bits)
+    assert sorted(order.tolist()) == list(range(len(xo)))
+    pos = np.empty(len(xo), np.int64)
+    pos[order] = np.arange(len(xo))
+    last_on_qubit = {}
+    last_random = -1
+    for j, x in enumerate(xo):
+        for q in x["qubits"]:
+            if q in last_on_qubit:
+                assert pos[last_on_qubit[q]] < pos[j], ("qubit order", q, j)
+            last_on_qubit[q] = j
+        if _is_ordered_random(x):
+            if last_random >= 0:
+                assert pos[last_random] < pos[j], ("random order", j)
+            last_random = j
+    n = circ["n_qubits"]
+    k = min(tile_q, n)
+    for p, m in enumerate(pmask):
+        assert bin(int(m)).count("1") == k
+    for d, j in enumerate(order):
+        qm = sum(1 << q for q in xo[j]["qubits"])
+        if len(xo[j]["qubits"]) < n:  # the final measure-all has its own pass
+            assert (qm & ~int(pmask[opass[d]])) == 0
+        if reg_bits > 0 and n > tile_q:
+            assert gw[ogrp[d]] <= reg_bits
+    # passes and groups are contiguous in device order
+    assert np.all(np.diff(opass) >= 0)
+    assert np.all(np.diff(ogrp) >= 0)
+
+
+def test_plan_reorders_to_fewer_passes_than_list_order():
+    w = W.workload("c3_20q")
+    order, opass, _, _, _ = _plan(w["circuit"], w["noise"], 13, 5)
+    layers = 60
+    assert opass.max() + 1 < 3 * layers  # list-order planning needs about 3 per layer
