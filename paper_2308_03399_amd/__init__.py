@@ -284,7 +284,8 @@ class Simulator:
         self.h = sv_batch_create(n_qubits, n_shots,
                                  SV_C128 if dtype == "c128" else SV_C64)
         sv_batch_set_option(self.h, "mode",
-                            {"batch": SV_MODE_BATCH, "branch": SV_MODE_BRANCH}[mode])
+                            {"batch": SV_MODE_BATCH, "branch": SV_MODE_BRANCH,
+                             "plain": SV_MODE_PLAIN}[mode])
         for k, v in options.items():
             sv_batch_set_option(self.h, k, int(v))
         self.device = torch.device(device)

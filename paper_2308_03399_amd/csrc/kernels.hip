@@ -212,16 +212,18 @@ __device__ __forceinline__ void put_uop(lds<UOp> *p, const UOp &u)
 
 // Micro-ops are the same for every thread: read them as scalars so that
 // their dispatch compiles to scalar branches, not exec-masked compares.
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ float uni(float v)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
 }
 __device__ __forceinline__ double uni(double v)
 {
+    // readfirstlane returns int: go through uint32_t so the low word is not
+    // sign-extended into the high word
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint64_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
-    const uint64_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
     return __builtin_bit_cast(double, lo | (hi << 32));
 }
 

@@ -36,7 +36,11 @@ hipError_t svb_counts(const uint64_t *memory, int64_t n, void *temp, size_t temp
                       uint64_t *keys_sorted, uint64_t *uniq, uint32_t *cnt, uint32_t *n_uniq,
                       hipStream_t st);
 size_t svb_counts_temp_bytes(int64_t n);
-hipError_t svb_plain_launch(int kind, const void *args, hipStream_t st);
+hipError_t svb_plain_run(int is_c128, const DevOp *ops, const DevOp *hops, int n_ops,
+                         const DevRule *rules, const DevRule *hrules, const double *pool, int n,
+                         uint64_t n_shots, uint64_t shot_base, uint64_t seed, void *state,
+                         uint64_t *memory, double *partial, int red_blocks, double *chunk,
+                         void *cell, double ro01, double ro10, hipStream_t st);
 }
 
 // ------------------------------------------------------------------ errors
@@ -61,6 +65,8 @@ static sv_status fail(sv_status s, const char *fmt, ...)
     } while (0)
 
 static uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+constexpr int kPlainRedBlocks = 1024;  // blocks of a plain-mode reduction
 
 // ------------------------------------------------------------------ handle
 struct sv_batch {
@@ -135,6 +141,13 @@ static sv_status derive(sv_batch *b)
     const bool r_ok = b->dtype == SV_C128 ? (r == 4 || r == 5) : (r == 5 || r == 6);
     b->use_groups = (!b->resident && r_ok && b->opt_engine == 0) ? 1 : 0;
     b->reg_bits = b->use_groups ? r : 0;
+    if (b->mode == SV_MODE_PLAIN) {  // one state, per-op kernels over the whole GPU
+        b->use_groups = 0;
+        b->reg_bits = 0;
+        b->workers = 1;
+        b->slots = 1;
+        return SV_OK;
+    }
     int per_cu = 0;
     HIPCHK(svb_exec_occupancy(b->dtype == SV_C128, b->tile_q, b->resident, b->reg_bits, &per_cu));
     if (per_cu < 1) return fail(SV_EDEVICE, "executor does not fit on a compute unit");
@@ -177,7 +190,10 @@ static void layout(sv_batch *b)
     L.ctl = take(sizeof(Control));
     L.free_slots = take((uint64_t)std::max(b->slots, 1) * 4);
     const uint64_t n_tiles = b->resident ? 1 : (1ull << (b->n - b->tile_q));
-    L.tile_sums = take((uint64_t)b->workers * n_tiles * 8);
+    uint64_t ts = (uint64_t)b->workers * n_tiles * 8;
+    if (b->mode == SV_MODE_PLAIN)  // partial sums, chunk sums and the decision cell
+        ts = (uint64_t)kPlainRedBlocks * 17 * 8 + (((1ull << b->n) + 255) / 256) * 8 + 64;
+    L.tile_sums = take(ts);
     L.dump = take(b->dump_shot >= 0 ? (16ull << b->n) : 8);
     L.counts_tmp = take(svb_counts_temp_bytes((int64_t)S));
     L.keys_sorted = take(S * 8);
@@ -715,7 +731,6 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
     if (sizing && b->attached) return fail(SV_ESTATE, "option %s must be set before attach", key);
     if (k == "mode") {
         if (v < 0 || v > 2) return fail(SV_EINVAL, "mode %lld", (long long)v);
-        if (v == SV_MODE_PLAIN) return fail(SV_EUNSUPPORTED, "plain mode is not built into this library");
         b->mode = (int)v;
     } else if (k == "slots") {
         if (v < 0 || v > (1 << 24)) return fail(SV_EINVAL, "slots %lld", (long long)v);
@@ -820,8 +835,26 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     // device program
     Plan plan;
     const uint32_t swz = b->dtype == SV_C128 ? 63u : 62u;
-    plan_program(n, b->tile_q, b->reg_bits, b->resident != 0, b->use_groups != 0, swz, xo, rules,
-                 terminal, plan);
+    const bool plain = b->mode == SV_MODE_PLAIN;
+    if (plain) {  // list order, one pass and one group holding everything
+        PassInfo pi;
+        std::memset(&pi, 0, sizeof pi);
+        pi.end_op = (uint32_t)xo.size();
+        GroupInfo gi;
+        std::memset(&gi, 0, sizeof gi);
+        gi.end_op = (uint32_t)xo.size();
+        gi.fallback = 1;
+        for (uint32_t j = 0; j < xo.size(); ++j) {
+            plan.order.push_back(j);
+            plan.op_pass.push_back(0);
+            plan.op_group.push_back(0);
+        }
+        plan.passes.push_back(pi);
+        plan.groups.push_back(gi);
+    } else {
+        plan_program(n, b->tile_q, b->reg_bits, b->resident != 0, b->use_groups != 0, swz, xo,
+                     rules, terminal, plan);
+    }
     const std::vector<PassInfo> &passes = plan.passes;
     std::vector<double> pool;
     std::vector<DevRule> drules(rules.size());
@@ -936,6 +969,38 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     P.resident = b->resident;
     P.use_groups = b->use_groups;
     P.swz = swz;
+
+    if (plain) {
+        double *scratch = (double *)(A + L.tile_sums);
+        double *chunk = scratch + (size_t)kPlainRedBlocks * 17;
+        void *cell = chunk + (((1ull << n) + 255) / 256);
+        HIPCHK(hipEventRecord(b->ev0, b->stream));
+        HIPCHK(hipEventRecord(b->ev2, b->stream));
+        HIPCHK(svb_plain_run(b->dtype == SV_C128, P.ops, dops.data(), P.n_ops, P.rules, drules.data(),
+                             P.pool, n, (uint64_t)b->shots, P.shot_base, seed, P.slots, P.memory,
+                             scratch, kPlainRedBlocks, chunk, cell, ro01, ro10, b->stream));
+        HIPCHK(hipEventRecord(b->ev3, b->stream));
+        HIPCHK(hipEventRecord(b->ev1, b->stream));
+        HIPCHK(hipEventSynchronize(b->ev1));
+        float ms = 0, ems = 0;
+        HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+        HIPCHK(hipEventElapsedTime(&ems, b->ev2, b->ev3));
+        sv_stats &st = b->stats;
+        std::memset(&st, 0, sizeof st);
+        st.kernel_ms = ms;
+        st.exec_ms = ems;
+        st.exec_launches = 1;
+        st.expanded_ops = xo.size();
+        st.gate_count = gate_count;
+        st.workers = 1;
+        st.slots = 1;
+        st.tile_qubits = (uint32_t)n;
+        st.passes = (uint64_t)b->shots * xo.size();
+        st.amp_bytes = st.passes * 2 * state_bytes(b);
+        b->have_results = true;
+        b->have_dump = false;
+        return SV_OK;
+    }
 
     const bool branch = P.branch_mode != 0;
     const int root_slot = (branch && !b->resident) ? 0 : -1;

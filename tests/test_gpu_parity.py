@@ -177,3 +177,25 @@ def test_shot_offset_waves_equal_one_job():
     b = gpu_run(circ, noise, 180, dtype="c128", seed=9, shot_offset=120)
     assert mismatches(a["memory"], exp[:120]) == 0
     assert mismatches(b["memory"], exp[120:]) == 0
+
+
+# ---------------------------------------------------------------------------
+# Plain per-shot form (one kernel per op over the whole state)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 9, 13])
+def test_plain_mode_matches_oracle(n):
+    circ = W.random_small(n, 60, seed=30 + n, n_mid=2)
+    noise = _noise_full(p1=0.05, p2=0.08, gamma=0.05)
+    shots = 40
+    say(f"case plain n={n}")
+    got = gpu_run(circ, noise, shots, dtype="c128", mode="plain", seed=3)
+    exp = oracle_memory(circ, noise, shots, seed=3)
+    assert mismatches(got["memory"], exp) == 0
+
+
+def test_plain_mode_c1_first_shots():
+    w = W.workload("c1_10q")
+    say("case plain c1 (100 shots)")
+    got = gpu_run(w["circuit"], w["noise"], 100, dtype="c128", mode="plain", seed=0)
+    exp = oracle_memory(w["circuit"], w["noise"], 100, seed=0)
+    assert mismatches(got["memory"], exp) == 0
