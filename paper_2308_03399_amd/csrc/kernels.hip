@@ -676,19 +676,30 @@ struct TileIO {
     using A = typename V2<R>::T;
     static constexpr int V = 16 / sizeof(A);
     static constexpr int NC = NR / V;
-    uint32_t gt;   // per-thread global byte offset
-    uint32_t pt;   // per-thread LDS byte position
+    static constexpr int LNC = NC >= 64 ? 6 : NC >= 32 ? 5 : NC >= 16 ? 4 : NC >= 8 ? 3 : NC >= 4 ? 2 : NC >= 2 ? 1 : 0;
+    uint32_t gt;        // per-thread global byte offset
+    uint32_t pt;        // per-thread LDS byte position
+    uint32_t gb[LNC + 1];  // global byte offset of chunk-index bit j (uniform)
 
     __device__ void setup(Ctx<R> &c)
     {
         const uint32_t l = (uint32_t)c.tid * V;
         gt = (c.hi_off[l >> 4] + (l & 15u)) * (uint32_t)sizeof(A);
         pt = c.at(l) * (uint32_t)sizeof(A);
+#pragma unroll
+        for (int j = 0; j < LNC; ++j)
+            gb[j] = __builtin_amdgcn_readfirstlane(c.hi_off[(uint32_t)((kWG * V) << j) >> 4] *
+                                                   (uint32_t)sizeof(A));
     }
-    __device__ __forceinline__ uint32_t gu(Ctx<R> &c, int u) const
+    // the deposit is linear over disjoint bits, so offsets of chunk u
+    // combine from per-bit offsets without a table lookup per tile
+    __device__ __forceinline__ uint32_t gu(Ctx<R> &, int u) const
     {
-        return __builtin_amdgcn_readfirstlane(c.hi_off[(uint32_t)(u * kWG * V) >> 4] *
-                                              (uint32_t)sizeof(A));
+        uint32_t g = 0;
+#pragma unroll
+        for (int j = 0; j < LNC; ++j)
+            if (u & (1 << j)) g ^= gb[j];
+        return g;
     }
     __device__ __forceinline__ uint32_t pu(Ctx<R> &c, int u) const
     {

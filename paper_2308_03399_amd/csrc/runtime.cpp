@@ -457,6 +457,25 @@ static int gf2_rank_add(uint32_t basis[6], uint32_t v)
     return 0;
 }
 
+// A gate and the channel ops the noise model attached to it (they follow it
+// in the expanded list, on a subset of its qubits) are placed as one unit:
+// taking a gate into a pass or group while deferring its channel would
+// split the fused one-qubit factor of that qubit into two micro-ops.
+static size_t unit_end(const std::vector<XOp> &xo, const std::vector<uint32_t> &list, size_t idx,
+                       const std::vector<Rule> &rules, bool groups)
+{
+    const XOp &g = xo[list[idx]];
+    size_t e = idx + 1;
+    if (g.kind < 0 || op_ordered(g) || (groups && op_fallback(g, rules))) return e;
+    const uint32_t m = qmask_of(g);
+    while (e < list.size() && list[e] == list[e - 1] + 1) {
+        const XOp &x = xo[list[e]];
+        if (x.kind >= 0 || (qmask_of(x) & ~m) || (groups && op_fallback(x, rules))) break;
+        ++e;
+    }
+    return e;
+}
+
 static void plan_program(int n, int k, int r, bool resident, bool use_groups, uint32_t swz,
                          const std::vector<XOp> &xo, const std::vector<Rule> &rules,
                          bool terminal, Plan &P)
@@ -493,14 +512,14 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
             std::vector<uint32_t> gsel, grest;
             uint32_t G = 0, blocked = 0;
             bool ord_blocked = false, fb_group = false;
-            for (size_t idx = 0; idx < grem.size(); ++idx) {
+            for (size_t idx = 0; idx < grem.size();) {
                 const uint32_t j = grem[idx];
                 const XOp &x = xo[j];
-                const uint32_t m = qmask_of(x);
-                const bool ord = op_ordered(x);
-                const bool ok = !(m & blocked) && !(ord && ord_blocked);
                 const bool fb = !use_groups || op_fallback(x, rules);
                 if (fb) {
+                    const uint32_t m = qmask_of(x);
+                    const bool ord = op_ordered(x);
+                    const bool ok = !(m & blocked) && !(ord && ord_blocked);
                     if (ok && gsel.empty()) {
                         gsel.push_back(j);
                         fb_group = true;
@@ -510,16 +529,26 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
                     blocked |= m;
                     ord_blocked |= ord;
                     grest.push_back(j);
+                    ++idx;
                     continue;
                 }
-                if (ok && __builtin_popcount(G | m) <= r) {
-                    gsel.push_back(j);
+                const size_t e = unit_end(xo, grem, idx, rules, true);
+                uint32_t m = 0;
+                bool ord = false;
+                for (size_t t = idx; t < e; ++t) {
+                    m |= qmask_of(xo[grem[t]]);
+                    ord = ord || op_ordered(xo[grem[t]]);
+                }
+                const bool ok = !(m & blocked) && !(ord && ord_blocked) &&
+                                __builtin_popcount(G | m) <= r;
+                for (size_t t = idx; t < e; ++t) (ok ? gsel : grest).push_back(grem[t]);
+                if (ok) {
                     G |= m;
                 } else {
                     blocked |= m;
                     ord_blocked |= ord;
-                    grest.push_back(j);
                 }
+                idx = e;
             }
             GroupInfo gi;
             std::memset(&gi, 0, sizeof gi);
@@ -579,25 +608,28 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
         std::vector<uint32_t> sel, rest;
         uint32_t T = base_mask, blocked = 0;
         bool ord_blocked = false;
-        for (size_t idx = 0; idx < remaining.size(); ++idx) {
-            const uint32_t j = remaining[idx];
-            if (sel.size() >= (size_t)kMaxPassOps) {
+        for (size_t idx = 0; idx < remaining.size();) {
+            const size_t e = unit_end(xo, remaining, idx, rules, false);
+            if (sel.size() + (e - idx) > (size_t)kMaxPassOps) {
                 rest.insert(rest.end(), remaining.begin() + idx, remaining.end());
                 break;
             }
-            const XOp &x = xo[j];
-            const uint32_t m = qmask_of(x);
-            const bool ord = op_ordered(x);
+            uint32_t m = 0;
+            bool ord = false;
+            for (size_t t = idx; t < e; ++t) {
+                m |= qmask_of(xo[remaining[t]]);
+                ord = ord || op_ordered(xo[remaining[t]]);
+            }
             const bool ok = !(m & blocked) && !(ord && ord_blocked) &&
                             __builtin_popcount(T | m) <= k;
+            for (size_t t = idx; t < e; ++t) (ok ? sel : rest).push_back(remaining[t]);
             if (ok) {
-                sel.push_back(j);
                 T |= m;
             } else {
                 blocked |= m;
                 ord_blocked |= ord;
-                rest.push_back(j);
             }
+            idx = e;
         }
         emit_pass(sel, T);
         remaining.swap(rest);
