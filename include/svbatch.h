@@ -143,7 +143,7 @@ typedef struct {
     uint64_t flops;            /* flops of the applied (fused) ops                 */
     double exec_ms;            /* device time of the executor launches only        */
     uint32_t exec_launches;    /* executor launches (1 + waiting-list relaunches)   */
-    uint32_t pad;
+    uint32_t tile_buffers;     /* LDS tile buffers of streamed grouped passes (1|2) */
     uint64_t groups;           /* register groups executed per sweep, summed       */
     uint64_t uops;             /* register micro-ops executed per sweep, summed    */
 } sv_stats;

@@ -84,7 +84,7 @@ class sv_stats(ctypes.Structure):
                 ("slots", ctypes.c_uint32), ("tile_qubits", ctypes.c_uint32),
                 ("static_passes", ctypes.c_uint32), ("flops", ctypes.c_uint64),
                 ("exec_ms", ctypes.c_double), ("exec_launches", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32), ("groups", ctypes.c_uint64),
+                ("tile_buffers", ctypes.c_uint32), ("groups", ctypes.c_uint64),
                 ("uops", ctypes.c_uint64)]
 
     def as_dict(self) -> Dict:

@@ -44,6 +44,18 @@ template <> struct V2<double> { using T = f64x2; };
 // accesses compile to ds_* and global_* instructions rather than flat ones.
 template <class T> using lds = __attribute__((address_space(3))) T;
 template <class T> using gbl = __attribute__((address_space(1))) T;
+// read-only program data (groups, passes) seen through the constant
+// address space: uniform reads become scalar loads, which leave the vector
+// memory counter to the tile copies in flight
+template <class T> using cst = __attribute__((address_space(4))) T;
+template <class T>
+__device__ __forceinline__ const cst<T> *to_const(const T *p)
+{
+    const uint64_t a = (uint64_t)p;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (const cst<T> *)(lo | (hi << 32));
+}
 
 // ------------------------------------------------------------------ RNG
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -80,6 +92,15 @@ __device__ __forceinline__ double wave_sum(double v)
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+
+// Workgroup barrier that orders LDS accesses only. __syncthreads() also
+// waits for the wave's global memory operations, which would stall on the
+// asynchronous tile copy in flight.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// wait until every vector memory operation of this wave has completed
+// (the asynchronous global->LDS copies included)
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t *p)
 {
@@ -243,14 +264,15 @@ __device__ __forceinline__ UOp get_uop(const lds<UOp> *p)
 
 // Byte offset of the per-workgroup state in dynamic LDS (after the tile,
 // the offset table, the decisions and the micro-op area).
-__device__ __forceinline__ uint32_t svb_side_bytes_dev(int tile_q, int amp_bytes, int resident)
+__device__ __forceinline__ uint32_t svb_side_bytes_dev(int tile_q, int amp_bytes, int resident,
+                                                      int nbuf)
 {
-    const uint32_t tile = (1u << tile_q) * amp_bytes;
+    const uint32_t tile = (1u << tile_q) * amp_bytes * (resident ? 1u : (uint32_t)nbuf);
     const uint32_t hi = resident ? 16u : (1u << (tile_q - kCoalesceQ)) * 4u;
     const uint32_t dec = kMaxPassOps * 2;
     const uint32_t fuse = kMaxPassGroups * 16 + kMaxPassUops * 8 + kPassMatBytes + 8 * 8 * 8;
     const uint32_t cnt = 16u * kWG * 4u;
-    const bool cnt_in_tile = !resident && tile >= cnt;
+    const bool cnt_in_tile = !resident && (1u << tile_q) * amp_bytes >= cnt;
     const uint32_t ua = (!cnt_in_tile && cnt > fuse) ? cnt : fuse;
     return (tile + hi + dec + ua + 15u) / 16u * 16u;
 }
@@ -261,6 +283,7 @@ struct Ctx {
     const ExecParams &P;
     lds<WgShared> &S;
     lds<A> *L;         // LDS tile (2^k amplitudes, swizzled positions)
+    uint32_t lbase;    // LDS byte address of L (0, or the second buffer)
     lds<uint32_t> *hi_off;  // LDS: global offset of local index bits >= 4
     lds<int16_t> *dec; // LDS: decided outcome of each op of the pass
     lds<int> *cnt;     // LDS: 16 x kWG outcome counters (splits); aliases the tile
@@ -621,36 +644,63 @@ __device__ __forceinline__ void d_two(A (&v)[NR], int kind, int c, int t)
 #undef SVB_P
 }
 
+// Values the tile loop needs, held in registers: the executor context
+// lives in private memory (cold paths take it by reference), and a private
+// load inside the loop would wait for the tile copies in flight.
+struct Hot {
+    uint32_t ug, uops, mats;  // LDS byte addresses of the pass's groups, micro-ops, matrices
+    uint32_t lbase;           // LDS byte address of the current tile buffer
+    uint32_t swm;             // swizzle mask
+    int n_ug, k, tid;
+    __device__ __forceinline__ uint32_t at(uint32_t i) const
+    {
+        return i ^ (((i >> 6) ^ (i >> 12)) & swm);
+    }
+};
+
 // Gather the thread's NR amplitudes of group gi from LDS, run the group's
 // micro-ops in registers, scatter back.
 template <class R, int NR>
-__device__ void run_group(Ctx<R> &c, const GroupInfo &gi, int first, int count)
+__device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi, int first, int count)
 {
     using A = typename V2<R>::T;
     constexpr int RB = NR == 64 ? 6 : NR == 32 ? 5 : NR == 16 ? 4 : 3;
     constexpr int SH = sizeof(A) == 8 ? 3 : 4;
+    // scalar loads are whole dwords: read the position bytes as words
+    const cst<uint32_t> *gw = (const cst<uint32_t> *)&gi;
+    uint32_t gpw[2], cpw[4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) gpw[i] = gw[offsetof(GroupInfo, gpos) / 4 + i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cpw[i] = gw[offsetof(GroupInfo, cpos) / 4 + i];
     uint32_t base = 0;
-    for (int i = 0; i < c.k - RB; ++i) base |= ((uint32_t)(c.tid >> i) & 1u) << gi.cpos[i];
+    for (int i = 0; i < h.k - RB; ++i)
+        base |= ((uint32_t)(h.tid >> i) & 1u) << ((cpw[i >> 2] >> (8 * (i & 3))) & 0xffu);
     // byte position of register i = (thread part) ^ (uniform part); the
-    // swizzle is linear over disjoint bits, so the parts combine by XOR
-    const uint32_t pb8 = c.at(base) << SH;
+    // swizzle is linear over disjoint bits, so the parts combine by XOR.
+    // A second tile buffer starts at the tile size, a power of two above
+    // every in-tile byte position, so OR-ing its base commutes with the XORs
+    const uint32_t pb8 = (h.at(base) << SH) | h.lbase;
     uint32_t pe8[RB];
 #pragma unroll
-    for (int j = 0; j < RB; ++j) pe8[j] = __builtin_amdgcn_readfirstlane(c.at(1u << gi.gpos[j]) << SH);
+    for (int j = 0; j < RB; ++j)
+        pe8[j] = __builtin_amdgcn_readfirstlane(h.at(1u << ((gpw[j >> 2] >> (8 * (j & 3))) & 0xffu)) << SH);
     uint32_t K[NR];
     K[0] = 0;
 #pragma unroll
     for (int i = 1; i < NR; ++i) K[i] = K[i & (i - 1)] ^ pe8[__builtin_ctz(i)];
-    // the tile starts at LDS address 0, so pb8 ^ K[i] is the address itself
+    // pb8 ^ K[i] is the LDS address itself
     A v[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) v[i] = *(const lds<A> *)(size_t)(pb8 ^ K[i]);
+    const lds<UOp> *uops = (const lds<UOp> *)(size_t)h.uops;
+    const lds<R> *mats = (const lds<R> *)(size_t)h.mats;
     for (int q = 0; q < count; ++q) {
-        const UOp u = get_uop(c.uops + first + q);
+        const UOp u = get_uop(uops + first + q);
         if (u.kind == UK_MAT1 || u.kind == UK_DIAG1) {
             R m[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) m[e] = uni(c.mats[u.mat * 8 + e]);
+            for (int e = 0; e < 8; ++e) m[e] = uni(mats[u.mat * 8 + e]);
             d_mat1<A, R, NR>(v, u.j0, m, u.kind == UK_DIAG1);
         } else {
             d_two<A, NR>(v, u.kind, u.j0, u.j1);
@@ -661,7 +711,7 @@ __device__ void run_group(Ctx<R> &c, const GroupInfo &gi, int first, int count)
     asm volatile("" : "+v"(pw));
 #pragma unroll
     for (int i = 0; i < NR; ++i) *(lds<A> *)(size_t)(pw ^ K[i]) = v[i];
-    __syncthreads();
+    lds_sync();
 }
 
 // Per-pass chunk offsets of a thread for streamed tile copies: global byte
@@ -735,6 +785,58 @@ struct TileIO {
             }
         }
         __syncthreads();
+    }
+
+    // ---- double-buffered streaming: LDS is filled and drained in linear
+    // order (16 bytes per lane, a wave covers 1 KB), so the next tile can
+    // be fetched straight into LDS with no registers while this one
+    // computes. LDS byte (u*kWG + t)*16 of a buffer holds tile index
+    // at(p), p = (u*kWG + t)*V; at() is its own inverse, so the amplitude
+    // of tile index l still sits at position at(l).
+    uint32_t lt;          // per-thread global byte offset of linear chunk 0
+    uint32_t lb[LNC + 1]; // global byte offset of linear chunk-index bit j (uniform)
+    uint32_t tid;
+
+    __device__ void setup_linear(Ctx<R> &c)
+    {
+        tid = (uint32_t)c.tid;
+        const uint32_t l = c.at((uint32_t)c.tid * V);
+        lt = (c.hi_off[l >> 4] + (l & 15u)) * (uint32_t)sizeof(A);
+#pragma unroll
+        for (int j = 0; j < LNC; ++j) {
+            const uint32_t m = c.at((uint32_t)((kWG * V) << j));
+            lb[j] = __builtin_amdgcn_readfirstlane((c.hi_off[m >> 4] + (m & 15u)) *
+                                                   (uint32_t)sizeof(A));
+        }
+    }
+    __device__ __forceinline__ uint32_t lu(int u) const
+    {
+        uint32_t g = 0;
+#pragma unroll
+        for (int j = 0; j < LNC; ++j)
+            if (u & (1 << j)) g ^= lb[j];
+        return g;
+    }
+    // Issue the asynchronous global->LDS copy of the tile at base into the
+    // buffer at LDS byte address buf; complete after wait_vm() + barrier.
+    __device__ void issue(const gbl<A> *Gt, uint64_t base, uint32_t buf) const
+    {
+        const gbl<unsigned char> *Gb = (const gbl<unsigned char> *)(Gt + base);
+        const uint32_t wb = __builtin_amdgcn_readfirstlane(buf + (tid & ~63u) * 16u);
+#pragma unroll
+        for (int u = 0; u < NC; ++u)
+            __builtin_amdgcn_global_load_lds((const gbl<void> *)(Gb + (lt ^ lu(u))),
+                                             (lds<void> *)(size_t)(wb + (uint32_t)u * kWG * 16u),
+                                             16, 0, 0);
+    }
+    __device__ void store_linear(gbl<A> *Gt, uint64_t base, uint32_t buf) const
+    {
+        gbl<unsigned char> *Gb = (gbl<unsigned char> *)(Gt + base);
+        const uint32_t p0 = buf + tid * 16u;
+#pragma unroll
+        for (int u = 0; u < NC; ++u)
+            *(gbl<u32x4> *)(Gb + (lt ^ lu(u))) =
+                *(const lds<u32x4> *)(size_t)(p0 + (uint32_t)u * kWG * 16u);
     }
 
     __device__ void store(Ctx<R> &c, gbl<A> *Gt, uint64_t base)
@@ -1016,6 +1118,16 @@ __device__ __forceinline__ uint64_t tile_base(const PassInfo &pi, int n, int k, 
 {
     uint64_t base = 0;
     for (int i = 0; i < n - k; ++i) base |= (uint64_t)((t >> i) & 1u) << pi.gq[i];
+    return base;
+}
+
+__device__ __forceinline__ uint64_t tile_base_c(const cst<PassInfo> &pi, int n, int k, uint32_t t)
+{
+    // scalar loads are whole dwords: read the qubit bytes as words
+    const cst<uint32_t> *w = (const cst<uint32_t> *)&pi + offsetof(PassInfo, gq) / 4;
+    uint64_t base = 0;
+    for (int i = 0; i < n - k; ++i)
+        base |= (uint64_t)((t >> i) & 1u) << ((w[i >> 2] >> (8 * (i & 3))) & 0xffu);
     return base;
 }
 
@@ -1477,31 +1589,30 @@ __device__ void apply_range(Ctx<R> &c, uint64_t &flops)
     }
 }
 
-// One sweep over the state: apply [start, end), then accumulate the
-// reduction of the stopping op if asked.
-template <class R, int NR>
-__device__ void run_groups(Ctx<R> &c, uint64_t &flops)
+// A fallback group: its ops run as LDS sweeps over the current tile.
+template <class R>
+__device__ __noinline__ void run_fallback(Ctx<R> &c, int a, int b)
 {
-    const ExecParams &P = c.P;
     lds<WgShared> &S = c.S;
-    const int n_ug = (int)uni((uint32_t)S.n_ug);
-    for (int u = 0; u < n_ug; ++u) {
-        const lds<UGroup> &gl = c.ug[u];
-        UGroup g;
-        g.gidx = (int32_t)uni((uint32_t)gl.gidx);
-        g.a = (int32_t)uni((uint32_t)gl.a);
-        g.b = (int32_t)uni((uint32_t)gl.b);
-        g.fallback = (int32_t)uni((uint32_t)gl.fallback);
-        if (g.fallback) {
-            for (int o = g.a; o < g.b; ++o) {
-                const double s = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
-                apply_op(c, P.ops[o], c.dec[o - S.start], s);
-            }
-        } else if constexpr (NR > 0) {
-            run_group<R, NR>(c, P.groups[g.gidx], g.a, g.b);
-        }
+    for (int o = a; o < b; ++o) {
+        const double s = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
+        apply_op(c, c.P.ops[o], c.dec[o - S.start], s);
     }
-    flops += S.pass_flops;
+}
+
+// The pass's groups on the current tile, in order.
+template <class R, int NR>
+__device__ __forceinline__ void run_groups(Ctx<R> &c, const Hot &h, const cst<GroupInfo> *groups)
+{
+    for (int u = 0; u < h.n_ug; ++u) {
+        const lds<UGroup> &gl = ((const lds<UGroup> *)(size_t)h.ug)[u];
+        const int gidx = (int)uni((uint32_t)gl.gidx);
+        const int a = (int)uni((uint32_t)gl.a);
+        const int b = (int)uni((uint32_t)gl.b);
+        const int fb = (int)uni((uint32_t)gl.fallback);
+        if (fb) run_fallback<R>(c, a, b);
+        else if constexpr (NR > 0) run_group<R, NR>(h, groups[gidx], a, b);
+    }
 }
 
 template <class R, int NR>
@@ -1529,14 +1640,52 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
         const bool fresh = S.fresh != 0;
         if constexpr (NR > 0) {
             if (P.use_groups) {
-                TileIO<R, NR> io;
-                io.setup(c);
-                for (uint32_t t = 0; t < c.n_tiles; ++t) {
-                    const uint64_t base = tile_base<R>(pi, n, k, t);
-                    io.load(c, G, base, fresh);
-                    if (grp) run_groups<R, NR>(c, flops);
-                    if (want_reduce) reduce_tile(c, rop, acc);
-                    if (has_ops) io.store(c, G, base);
+                Hot h;
+                h.ug = (uint32_t)(size_t)c.ug;
+                h.uops = (uint32_t)(size_t)c.uops;
+                h.mats = (uint32_t)(size_t)c.mats;
+                h.lbase = 0;
+                h.swm = uni(c.swm);
+                h.n_ug = (int)uni((uint32_t)S.n_ug);
+                h.k = k;
+                h.tid = c.tid;
+                const cst<GroupInfo> *groups = to_const(P.groups);
+                const cst<PassInfo> &pc = *to_const(&pi);
+                if (P.nbuf == 2 && !fresh) {
+                    TileIO<R, NR> io;
+                    io.setup_linear(c);
+                    // nothing below may read private memory: such a load
+                    // would wait for the tile copy in flight
+                    const uint32_t tb = uni((1u << k) * (uint32_t)sizeof(A));  // buffer 1 starts here
+                    const uint32_t nt = uni(1u << (n - k));
+                    lds<A> *const L0 = c.L;
+                    io.issue(G, tile_base_c(pc, n, k, 0), 0);
+                    for (uint32_t t = 0; t < nt; ++t) {
+                        const uint32_t cur = (t & 1u) ? tb : 0u;
+                        wait_vm();
+                        __syncthreads();
+                        if (t + 1 < nt) io.issue(G, tile_base_c(pc, n, k, t + 1), cur ^ tb);
+                        h.lbase = cur;
+                        c.lbase = cur;  // cold paths (fallback groups, reductions) use c.L
+                        c.L = (lds<A> *)((lds<unsigned char> *)L0 + cur);
+                        if (grp) run_groups<R, NR>(c, h, groups);
+                        if (want_reduce) reduce_tile(c, rop, acc);
+                        if (has_ops) io.store_linear(G, tile_base_c(pc, n, k, t), cur);
+                    }
+                    c.lbase = 0;
+                    c.L = L0;
+                    wait_vm();
+                    __syncthreads();
+                } else {
+                    TileIO<R, NR> io;
+                    io.setup(c);
+                    for (uint32_t t = 0; t < c.n_tiles; ++t) {
+                        const uint64_t base = tile_base_c(pc, n, k, t);
+                        io.load(c, G, base, fresh);
+                        if (grp) run_groups<R, NR>(c, h, groups);
+                        if (want_reduce) reduce_tile(c, rop, acc);
+                        if (has_ops) io.store(c, G, base);
+                    }
                 }
             }
         }
@@ -1544,8 +1693,7 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
             for (uint32_t t = 0; t < c.n_tiles; ++t) {
                 const uint64_t base = tile_base<R>(pi, n, k, t);
                 load_tile(c, G, base, fresh);
-                if (grp) run_groups<R, NR>(c, flops);
-                else apply_range(c, flops);
+                apply_range(c, flops);
                 if (want_reduce) {
                     reduce_tile(c, rop, acc);
                 }
@@ -1832,7 +1980,8 @@ __global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
     // no static LDS: the tile starts at LDS address 0 and the per-workgroup
     // state sits at the end of the dynamic allocation
     lds<unsigned char> *sm0 = (lds<unsigned char> *)smem;
-    lds<WgShared> &S = *(lds<WgShared> *)(sm0 + svb_side_bytes_dev(P.tile_q, (int)sizeof(A), P.resident));
+    lds<WgShared> &S =
+        *(lds<WgShared> *)(sm0 + svb_side_bytes_dev(P.tile_q, (int)sizeof(A), P.resident, P.nbuf));
     const int tid = threadIdx.x;
     const int n = P.n_qubits, k = P.tile_q;
     Ctx<R> c{P, S};
@@ -1843,7 +1992,8 @@ __global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
     c.n_tiles = P.resident ? 1u : (1u << (n - k));
     lds<unsigned char> *sm = sm0;
     c.L = (lds<A> *)sm;
-    c.hi_off = (lds<uint32_t> *)(sm + (size_t)c.tsize * sizeof(A));
+    c.lbase = 0;
+    c.hi_off = (lds<uint32_t> *)(sm + (size_t)c.tsize * sizeof(A) * (P.resident ? 1 : P.nbuf));
     const uint32_t n_hi = P.resident ? 4u : (1u << (k - kCoalesceQ));
     c.dec = (lds<int16_t> *)(c.hi_off + n_hi);
     lds<unsigned char> *uarea = (lds<unsigned char> *)(c.dec + kMaxPassOps);
@@ -2058,13 +2208,14 @@ static size_t uarea_bytes(int cnt_in_tile)
     return (!cnt_in_tile && cnt > fuse) ? cnt : fuse;
 }
 
-extern "C" size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident)
+extern "C" size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident, int nbuf)
 {
     const size_t tile = ((size_t)1 << tile_q) * amp_bytes;
+    const size_t tiles = tile * (resident ? 1 : nbuf);
     const size_t hi = resident ? 4 * 4 : ((size_t)1 << (tile_q - svb::kCoalesceQ)) * 4;
     const size_t dec = svb::kMaxPassOps * 2;
     const int cnt_in_tile = !resident && tile >= 16u * svb::kWG * 4u;
-    const size_t side = (tile + hi + dec + uarea_bytes(cnt_in_tile) + 15) / 16 * 16;
+    const size_t side = (tiles + hi + dec + uarea_bytes(cnt_in_tile) + 15) / 16 * 16;
     return side + sizeof(svb::WgShared);
 }
 
@@ -2101,9 +2252,9 @@ static hipError_t launch_one(const svb::ExecParams *P, int workers, size_t lds, 
 }
 
 static hipError_t dispatch(const svb::ExecParams *P, int is_c128, int reg_bits, int tile_q,
-                           int resident, int workers, hipStream_t st, int *occ)
+                           int resident, int nbuf, int workers, hipStream_t st, int *occ)
 {
-    const size_t lds = svb_exec_lds_bytes(tile_q, is_c128 ? 16 : 8, resident);
+    const size_t lds = svb_exec_lds_bytes(tile_q, is_c128 ? 16 : 8, resident, nbuf);
     if (is_c128) {
         if (reg_bits == 5) return launch_one<double, 32>(P, workers, lds, st, occ);
         if (reg_bits == 4) return launch_one<double, 16>(P, workers, lds, st, occ);
@@ -2119,13 +2270,13 @@ extern "C" {
 hipError_t svb_launch_exec(const svb::ExecParams *P, int is_c128, int reg_bits, int workers,
                            hipStream_t st)
 {
-    return dispatch(P, is_c128, reg_bits, P->tile_q, P->resident, workers, st, nullptr);
+    return dispatch(P, is_c128, reg_bits, P->tile_q, P->resident, P->nbuf, workers, st, nullptr);
 }
 
-hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int reg_bits,
+hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int reg_bits, int nbuf,
                               int *blocks_per_cu)
 {
-    return dispatch(nullptr, is_c128, reg_bits, tile_q, resident, 0, nullptr, blocks_per_cu);
+    return dispatch(nullptr, is_c128, reg_bits, tile_q, resident, nbuf, 0, nullptr, blocks_per_cu);
 }
 
 }  // extern "C"

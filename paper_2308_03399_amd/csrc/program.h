@@ -156,6 +156,8 @@ struct ExecParams {
     int32_t resident;        // 1: whole state in LDS (n <= k)
     int32_t use_groups;      // 1: streamed passes run register groups
     uint32_t swz;            // LDS swizzle mask of streamed passes
+    int32_t nbuf;            // LDS tile buffers of streamed grouped passes (1, or 2:
+                             // the next tile is fetched while this one computes)
 };
 
 }  // namespace svb

@@ -29,9 +29,9 @@ hipError_t svb_launch_init(const ExecParams *P, int restart, int n_root, int roo
 hipError_t svb_launch_restart(const ExecParams *P, int n_wait, hipStream_t st);
 hipError_t svb_launch_exec(const ExecParams *P, int is_c128, int reg_bits, int workers,
                            hipStream_t st);
-hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int reg_bits,
+hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int reg_bits, int nbuf,
                               int *blocks_per_cu);
-size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident);
+size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident, int nbuf);
 hipError_t svb_counts(const uint64_t *memory, int64_t n, void *temp, size_t temp_bytes,
                       uint64_t *keys_sorted, uint64_t *uniq, uint32_t *cnt, uint32_t *n_uniq,
                       hipStream_t st);
@@ -84,6 +84,8 @@ struct sv_batch {
     int tile_q = 0, resident = 0, workers = 0, slots = 0;
     int use_groups = 0, reg_bits = 0;  // register-group engine, log2(amps per thread)
     int64_t opt_engine = 0;            // 0 automatic, 1 LDS sweeps only
+    int64_t opt_pipeline = -1;         // -1 automatic, 0 one tile buffer, 1 two
+    int nbuf = 1;                      // LDS tile buffers of grouped streamed passes
     int cus = 0;
     int64_t wallclock_khz = 100000;
     // arena
@@ -105,6 +107,9 @@ struct sv_batch {
 static int amp_bytes(const sv_batch *b) { return b->dtype == SV_C128 ? 16 : 8; }
 static uint64_t state_bytes(const sv_batch *b) { return (uint64_t)amp_bytes(b) << b->n; }
 
+// tile buffers when the caller leaves the choice to the library
+constexpr int kAutoTileBuffers = 1;
+
 static sv_status derive(sv_batch *b)
 {
     int dev = 0;
@@ -121,14 +126,23 @@ static sv_status derive(sv_batch *b)
     if (prop.maxSharedMemoryPerMultiProcessor > 0)
         lds_cap = std::min(lds_cap, (size_t)prop.maxSharedMemoryPerMultiProcessor);
     const size_t static_lds = 0;  // the executor keeps all its LDS state in the dynamic block
+    // two tile buffers: the next tile is fetched into LDS while the
+    // current one computes, one workgroup per compute unit at the largest
+    // tile; one buffer: two workgroups per compute unit overlap instead
+    int nbuf = b->opt_pipeline == 0 ? 1 : (b->opt_pipeline == 1 ? 2 : kAutoTileBuffers);
+    auto fits = [&](int kk, int nb, int per_cu) {
+        return (size_t)per_cu * (svb_exec_lds_bytes(kk, amp_bytes(b), 0, nb) + static_lds) <= lds_cap;
+    };
     int kmax = b->dtype == SV_C128 ? 13 : kMaxTileQ;
-    while (kmax > 6 && svb_exec_lds_bytes(kmax, amp_bytes(b), 0) + static_lds > lds_cap) --kmax;
-    // default: the largest tile of which two workgroups fit on a compute unit
-    // (one streams its tile while the other computes)
+    while (kmax > 6 && !fits(kmax, nbuf, 1)) --kmax;
     int kdef = kmax;
-    while (kdef > 6 && 2 * (svb_exec_lds_bytes(kdef, amp_bytes(b), 0) + static_lds) > lds_cap) --kdef;
+    if (nbuf == 1)
+        while (kdef > 6 && !fits(kdef, 1, 2)) --kdef;
     int k = b->opt_tile > 0 ? (int)b->opt_tile : kdef;
-    if (k > kmax) k = kmax;
+    if (k > kmax) {
+        if (b->opt_pipeline != 1 && fits(k, 1, 1)) nbuf = 1;  // a larger tile wins over the pipeline
+        else k = kmax;
+    }
     if (b->n <= k) {
         b->resident = 1;
         b->tile_q = b->n;
@@ -141,6 +155,7 @@ static sv_status derive(sv_batch *b)
     const bool r_ok = b->dtype == SV_C128 ? (r == 4 || r == 5) : (r == 5 || r == 6);
     b->use_groups = (!b->resident && r_ok && b->opt_engine == 0) ? 1 : 0;
     b->reg_bits = b->use_groups ? r : 0;
+    b->nbuf = b->use_groups ? nbuf : 1;
     if (b->mode == SV_MODE_PLAIN) {  // one state, per-op kernels over the whole GPU
         b->use_groups = 0;
         b->reg_bits = 0;
@@ -149,7 +164,8 @@ static sv_status derive(sv_batch *b)
         return SV_OK;
     }
     int per_cu = 0;
-    HIPCHK(svb_exec_occupancy(b->dtype == SV_C128, b->tile_q, b->resident, b->reg_bits, &per_cu));
+    HIPCHK(svb_exec_occupancy(b->dtype == SV_C128, b->tile_q, b->resident, b->reg_bits, b->nbuf,
+                              &per_cu));
     if (per_cu < 1) return fail(SV_EDEVICE, "executor does not fit on a compute unit");
     int64_t w = b->opt_workers > 0 ? b->opt_workers : (int64_t)per_cu * b->cus;
     if (b->mode == SV_MODE_BATCH) w = std::min<int64_t>(w, b->shots);
@@ -759,7 +775,8 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
     if (!b || !key) return fail(SV_EINVAL, "NULL argument");
     const std::string k = key;
     const bool sizing = k == "mode" || k == "slots" || k == "workers" || k == "tile_qubits" ||
-                        k == "program_bytes" || k == "dump_shot" || k == "engine";
+                        k == "program_bytes" || k == "dump_shot" || k == "engine" ||
+                        k == "pipeline";
     if (sizing && b->attached) return fail(SV_ESTATE, "option %s must be set before attach", key);
     if (k == "mode") {
         if (v < 0 || v > 2) return fail(SV_EINVAL, "mode %lld", (long long)v);
@@ -782,6 +799,9 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
     } else if (k == "engine") {
         if (v < 0 || v > 1) return fail(SV_EINVAL, "engine %lld (0 automatic, 1 LDS sweeps)", (long long)v);
         b->opt_engine = v;
+    } else if (k == "pipeline") {
+        if (v < -1 || v > 1) return fail(SV_EINVAL, "pipeline %lld (-1 automatic, 0, 1)", (long long)v);
+        b->opt_pipeline = v;
     } else if (k == "shot_offset") {
         if (v < 0) return fail(SV_EINVAL, "shot_offset %lld", (long long)v);
         b->shot_offset = v;
@@ -1001,6 +1021,7 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     P.resident = b->resident;
     P.use_groups = b->use_groups;
     P.swz = swz;
+    P.nbuf = b->nbuf;
 
     if (plain) {
         double *scratch = (double *)(A + L.tile_sums);
@@ -1080,6 +1101,7 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     st.workers = (uint32_t)b->workers;
     st.slots = (uint32_t)b->slots;
     st.tile_qubits = (uint32_t)b->tile_q;
+    st.tile_buffers = (uint32_t)b->nbuf;
     st.static_passes = (uint32_t)passes.size();
     st.flops = acc[ST_FLOPS];
     st.exec_ms = exec_ms;

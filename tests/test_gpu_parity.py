@@ -124,17 +124,20 @@ def test_c64_agreement_and_tvd():
 # ---------------------------------------------------------------------------
 # Register-group engine (tiles of 2^k with k = 8 + log2(amplitudes/thread))
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("dtype,tile,n", [("c64", 14, 16), ("c64", 13, 15),
-                                          ("c128", 13, 15), ("c128", 12, 14)])
-def test_group_engine_matches_oracle(dtype, tile, n):
+@pytest.mark.parametrize("dtype,tile,n,pipe", [("c64", 14, 16, 0), ("c64", 13, 15, 0),
+                                               ("c128", 13, 15, 0), ("c128", 12, 14, 0),
+                                               ("c64", 13, 15, 1), ("c64", 13, 17, 1),
+                                               ("c128", 12, 14, 1)])
+def test_group_engine_matches_oracle(dtype, tile, n, pipe):
     circ = W.random_layered(n, 5, seed=21, mid_measure=(2, (0, n - 1)))
     noise = _noise_full(p1=0.02, p2=0.04, gamma=0.03)
     shots = 64
-    say(f"case groups dtype={dtype} tile={tile} n={n} shots={shots}")
-    got = gpu_run(circ, noise, shots, dtype=dtype, seed=5, tile_qubits=tile)
+    say(f"case groups dtype={dtype} tile={tile} n={n} pipeline={pipe} shots={shots}")
+    got = gpu_run(circ, noise, shots, dtype=dtype, seed=5, tile_qubits=tile, pipeline=pipe)
     exp = oracle_memory(circ, noise, shots, seed=5)
     st = got["stats"]
     assert st["tile_qubits"] == tile
+    assert st["tile_buffers"] == 1 + pipe
     bad = mismatches(got["memory"], exp)
     if dtype == "c128":
         assert bad == 0
@@ -142,26 +145,30 @@ def test_group_engine_matches_oracle(dtype, tile, n):
         assert bad <= 1
 
 
-@pytest.mark.parametrize("dtype,tile", [("c64", 14), ("c128", 13)])
-def test_group_engine_state_dump(dtype, tile):
+@pytest.mark.parametrize("dtype,tile,pipe", [("c64", 14, 0), ("c128", 13, 0),
+                                             ("c64", 13, 1), ("c128", 12, 1)])
+def test_group_engine_state_dump(dtype, tile, pipe):
     n = 15
     circ = W.random_small(n, 120, seed=4, measure_all=True)
     noise = _noise_full(p1=0.3, p2=0.3, gamma=0.3)
-    say(f"case groups dump dtype={dtype}")
-    got = gpu_run(circ, noise, 4, dtype=dtype, seed=1, dump_shot=2, tile_qubits=tile)
+    say(f"case groups dump dtype={dtype} tile={tile} pipeline={pipe}")
+    got = gpu_run(circ, noise, 4, dtype=dtype, seed=1, dump_shot=2, tile_qubits=tile,
+                  pipeline=pipe)
+    assert got["stats"]["tile_buffers"] == 1 + pipe
     _, psi = oracle.run(circ, noise, [2], seed=1,
                         stop_at=len_expanded(circ, noise) - 1, want_state=True)
     tol = 1e-11 if dtype == "c128" else 5e-5
     assert np.max(np.abs(got["state"] - psi)) < tol
 
 
-def test_group_engine_branch_mode():
+@pytest.mark.parametrize("pipe", [0, 1])
+def test_group_engine_branch_mode(pipe):
     n = 15
     circ = W.random_layered(n, 4, seed=8, mid_measure=(2, (3,)))
     noise = _noise_full(p1=0.01, p2=0.02, gamma=0.02)
     shots = 256
-    say("case groups branch mode")
-    got = gpu_run(circ, noise, shots, dtype="c128", mode="branch", seed=6)
+    say(f"case groups branch mode pipeline={pipe}")
+    got = gpu_run(circ, noise, shots, dtype="c128", mode="branch", seed=6, pipeline=pipe)
     exp = oracle_memory(circ, noise, shots, seed=6)
     assert mismatches(got["memory"], exp) == 0
     assert got["stats"]["branches"] > 0
