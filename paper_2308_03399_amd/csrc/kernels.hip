@@ -2262,6 +2262,7 @@ static hipError_t dispatch(const svb::ExecParams *P, int is_c128, int reg_bits, 
     }
     if (reg_bits == 6) return launch_one<float, 64>(P, workers, lds, st, occ);
     if (reg_bits == 5) return launch_one<float, 32>(P, workers, lds, st, occ);
+    if (reg_bits == 4) return launch_one<float, 16>(P, workers, lds, st, occ);
     return launch_one<float, 0>(P, workers, lds, st, occ);
 }
 

@@ -152,7 +152,7 @@ static sv_status derive(sv_batch *b)
     }
     // register groups need 2^k = kWG * 2^r amplitudes per tile
     const int r = b->tile_q - 8;
-    const bool r_ok = b->dtype == SV_C128 ? (r == 4 || r == 5) : (r == 5 || r == 6);
+    const bool r_ok = b->dtype == SV_C128 ? (r == 4 || r == 5) : (r >= 4 && r <= 6);
     b->use_groups = (!b->resident && r_ok && b->opt_engine == 0) ? 1 : 0;
     b->reg_bits = b->use_groups ? r : 0;
     b->nbuf = b->use_groups ? nbuf : 1;

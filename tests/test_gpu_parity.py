@@ -127,7 +127,8 @@ def test_c64_agreement_and_tvd():
 @pytest.mark.parametrize("dtype,tile,n,pipe", [("c64", 14, 16, 0), ("c64", 13, 15, 0),
                                                ("c128", 13, 15, 0), ("c128", 12, 14, 0),
                                                ("c64", 13, 15, 1), ("c64", 13, 17, 1),
-                                               ("c128", 12, 14, 1)])
+                                               ("c128", 12, 14, 1), ("c64", 12, 14, 0),
+                                               ("c64", 12, 14, 1)])
 def test_group_engine_matches_oracle(dtype, tile, n, pipe):
     circ = W.random_layered(n, 5, seed=21, mid_measure=(2, (0, n - 1)))
     noise = _noise_full(p1=0.02, p2=0.04, gamma=0.03)
