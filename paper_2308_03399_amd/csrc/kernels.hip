@@ -727,19 +727,20 @@ struct TileIO {
     static constexpr int V = 16 / sizeof(A);
     static constexpr int NC = NR / V;
     static constexpr int LNC = NC >= 64 ? 6 : NC >= 32 ? 5 : NC >= 16 ? 4 : NC >= 8 ? 3 : NC >= 4 ? 2 : NC >= 2 ? 1 : 0;
-    uint32_t gt;        // per-thread global byte offset
+    // Global offsets are kept in 16-byte chunks (the size of one copy),
+    // so 32 bits reach every byte of a state of up to 64 GiB.
+    uint32_t gt;        // per-thread global chunk offset
     uint32_t pt;        // per-thread LDS byte position
-    uint32_t gb[LNC + 1];  // global byte offset of chunk-index bit j (uniform)
+    uint32_t gb[LNC + 1];  // global chunk offset of chunk-index bit j (uniform)
 
     __device__ void setup(Ctx<R> &c)
     {
         const uint32_t l = (uint32_t)c.tid * V;
-        gt = (c.hi_off[l >> 4] + (l & 15u)) * (uint32_t)sizeof(A);
+        gt = (c.hi_off[l >> 4] + (l & 15u)) / V;
         pt = c.at(l) * (uint32_t)sizeof(A);
 #pragma unroll
         for (int j = 0; j < LNC; ++j)
-            gb[j] = __builtin_amdgcn_readfirstlane(c.hi_off[(uint32_t)((kWG * V) << j) >> 4] *
-                                                   (uint32_t)sizeof(A));
+            gb[j] = __builtin_amdgcn_readfirstlane(c.hi_off[(uint32_t)((kWG * V) << j) >> 4] / V);
     }
     // the deposit is linear over disjoint bits, so offsets of chunk u
     // combine from per-bit offsets without a table lookup per tile
@@ -761,7 +762,7 @@ struct TileIO {
         if (fresh) {
 #pragma unroll
             for (int u = 0; u < NC; ++u) {
-                const uint64_t g = base + (gt + gu(c, u)) / sizeof(A);
+                const uint64_t g = base + (uint64_t)(gt + gu(c, u)) * V;
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
                     A z;
@@ -771,14 +772,14 @@ struct TileIO {
                 }
             }
         } else {
-            const gbl<unsigned char> *Gb = (const gbl<unsigned char> *)(Gt + base);
+            const gbl<u32x4> *G16 = (const gbl<u32x4> *)(Gt + base);
             constexpr int BATCH = NC < 16 ? NC : 16;
 #pragma unroll
             for (int u0 = 0; u0 < NC; u0 += BATCH) {
                 u32x4 x[BATCH];
 #pragma unroll
                 for (int u = 0; u < BATCH; ++u)
-                    x[u] = *(const gbl<u32x4> *)(Gb + gu(c, u0 + u) + gt);
+                    x[u] = G16[gu(c, u0 + u) + gt];
 #pragma unroll
                 for (int u = 0; u < BATCH; ++u)
                     *(lds<u32x4> *)(size_t)(pt ^ pu(c, u0 + u)) = x[u];
@@ -793,20 +794,19 @@ struct TileIO {
     // computes. LDS byte (u*kWG + t)*16 of a buffer holds tile index
     // at(p), p = (u*kWG + t)*V; at() is its own inverse, so the amplitude
     // of tile index l still sits at position at(l).
-    uint32_t lt;          // per-thread global byte offset of linear chunk 0
-    uint32_t lb[LNC + 1]; // global byte offset of linear chunk-index bit j (uniform)
+    uint32_t lt;          // per-thread global chunk offset of linear chunk 0
+    uint32_t lb[LNC + 1]; // global chunk offset of linear chunk-index bit j (uniform)
     uint32_t tid;
 
     __device__ void setup_linear(Ctx<R> &c)
     {
         tid = (uint32_t)c.tid;
         const uint32_t l = c.at((uint32_t)c.tid * V);
-        lt = (c.hi_off[l >> 4] + (l & 15u)) * (uint32_t)sizeof(A);
+        lt = (c.hi_off[l >> 4] + (l & 15u)) / V;
 #pragma unroll
         for (int j = 0; j < LNC; ++j) {
             const uint32_t m = c.at((uint32_t)((kWG * V) << j));
-            lb[j] = __builtin_amdgcn_readfirstlane((c.hi_off[m >> 4] + (m & 15u)) *
-                                                   (uint32_t)sizeof(A));
+            lb[j] = __builtin_amdgcn_readfirstlane((c.hi_off[m >> 4] + (m & 15u)) / V);
         }
     }
     __device__ __forceinline__ uint32_t lu(int u) const
@@ -821,30 +821,30 @@ struct TileIO {
     // buffer at LDS byte address buf; complete after wait_vm() + barrier.
     __device__ void issue(const gbl<A> *Gt, uint64_t base, uint32_t buf) const
     {
-        const gbl<unsigned char> *Gb = (const gbl<unsigned char> *)(Gt + base);
+        const gbl<u32x4> *G16 = (const gbl<u32x4> *)(Gt + base);
         const uint32_t wb = __builtin_amdgcn_readfirstlane(buf + (tid & ~63u) * 16u);
 #pragma unroll
         for (int u = 0; u < NC; ++u)
-            __builtin_amdgcn_global_load_lds((const gbl<void> *)(Gb + (lt ^ lu(u))),
+            __builtin_amdgcn_global_load_lds((const gbl<void> *)(G16 + (lt ^ lu(u))),
                                              (lds<void> *)(size_t)(wb + (uint32_t)u * kWG * 16u),
                                              16, 0, 0);
     }
     __device__ void store_linear(gbl<A> *Gt, uint64_t base, uint32_t buf) const
     {
-        gbl<unsigned char> *Gb = (gbl<unsigned char> *)(Gt + base);
+        gbl<u32x4> *G16 = (gbl<u32x4> *)(Gt + base);
         const uint32_t p0 = buf + tid * 16u;
 #pragma unroll
         for (int u = 0; u < NC; ++u)
-            *(gbl<u32x4> *)(Gb + (lt ^ lu(u))) =
+            G16[lt ^ lu(u)] =
                 *(const lds<u32x4> *)(size_t)(p0 + (uint32_t)u * kWG * 16u);
     }
 
     __device__ void store(Ctx<R> &c, gbl<A> *Gt, uint64_t base)
     {
-        gbl<unsigned char> *Gb = (gbl<unsigned char> *)(Gt + base);
+        gbl<u32x4> *G16 = (gbl<u32x4> *)(Gt + base);
 #pragma unroll
         for (int u = 0; u < NC; ++u)
-            *(gbl<u32x4> *)(Gb + gu(c, u) + gt) = *(const lds<u32x4> *)(size_t)(pt ^ pu(c, u));
+            G16[gu(c, u) + gt] = *(const lds<u32x4> *)(size_t)(pt ^ pu(c, u));
         __syncthreads();
     }
 };

@@ -207,3 +207,23 @@ def test_plain_mode_c1_first_shots():
     got = gpu_run(w["circuit"], w["noise"], 100, dtype="c128", mode="plain", seed=0)
     exp = oracle_memory(w["circuit"], w["noise"], 100, seed=0)
     assert mismatches(got["memory"], exp) == 0
+
+
+def test_largest_state_offsets_beyond_32_bits():
+    # 29 qubits in complex128 is an 8 GiB state: tile copies address it with
+    # offsets past 2^32 bytes
+    n = 29
+    ops = [{"kind": "u3", "qubits": [q], "params": [0.3 + 0.1 * q, 0.2, 0.1]} for q in (0, 13, 27, 28)]
+    ops += [{"kind": "cx", "qubits": [28, 2]}, {"kind": "cx", "qubits": [14, 28]},
+            {"kind": "u3", "qubits": [28], "params": [1.1, 0.4, -0.3]},
+            {"kind": "measure", "qubits": [28, 27, 2, 0], "clbits": [0, 1, 2, 3]}]
+    circ = {"n_qubits": n, "ops": ops}
+    noise = W.noise_model([W.rule(["u3"], W.depolarizing_pauli(0.2, 1))])
+    say("case largest state n=29 c128")
+    got = gpu_run(circ, noise, 2, dtype="c128", seed=3, dump_shot=1)
+    exp = oracle_memory(circ, noise, 2, seed=3)
+    assert mismatches(got["memory"], exp) == 0
+    # the last op is not a terminal measure-all, so the dump follows it
+    _, psi = oracle.run(circ, noise, [1], seed=3, stop_at=len_expanded(circ, noise),
+                        want_state=True)
+    assert np.max(np.abs(got["state"] - psi)) < 1e-12
