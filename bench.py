@@ -62,6 +62,28 @@ def cpu_baseline(circ, noise, gate_count: int, seed: int):
                       f"(one shot per core, {dt:.1f} s wall)"}
 
 
+def other_form(circ, noise, seed, gates, shots, dtype, mode):
+    """One timed wave of the same workload in another precision or form
+    (shot ids 0..shots-1), for the comparisons the metric names."""
+    import torch
+    from paper_2308_03399_amd import Simulator
+    sim = Simulator(circ["n_qubits"], shots, dtype=dtype, mode=mode)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(circ, noise, seed=seed)
+    counts = sim.counts(capacity=shots)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = sim.stats()
+    sim.close()
+    assert sum(counts.values()) == shots
+    return {"dtype": dtype, "mode": mode, "shots": shots,
+            "value": shots * gates / dt, "unit": "shots*gates/s",
+            "ms": round(dt * 1e3, 1),
+            "hbm_gbs": round(st["amp_bytes"] / (st["exec_ms"] * 1e-3) / 1e9, 1)
+            if st["exec_ms"] > 0 else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +93,10 @@ def main():
     ap.add_argument("--mode", default="batch", choices=["batch", "branch"])
     ap.add_argument("--shots-per-step", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c128", action="store_true",
+                    help="skip the complex128 wave reported beside the c64 value")
+    ap.add_argument("--plain-shots", type=int, default=16,
+                    help="shots of the plain per-shot FP64 form timed for the speedup (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: shots shard across GPUs by "
@@ -164,9 +190,17 @@ def main():
         },
         "roofline": roof,
     }
+    sim.close()
+    if not args.no_c128 and args.dtype == "c64":
+        out["c128"] = other_form(circ, noise, seed, gates, B, "c128", args.mode)
+    if args.plain_shots > 0:
+        pl = other_form(circ, noise, seed, gates, args.plain_shots, "c128", "plain")
+        pl["note"] = ("plain per-shot FP64 form: one state, one kernel per op, first "
+                      f"{args.plain_shots} shot ids; time is linear in shots for this form")
+        pl["speedup_of_value"] = round(value / pl["value"], 1)
+        out["plain_fp64"] = pl
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(circ, noise, gates, seed)
-    sim.close()
     print(json.dumps(out), flush=True)
 
 
