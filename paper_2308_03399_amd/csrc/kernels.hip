@@ -284,7 +284,7 @@ struct Ctx {
     lds<WgShared> &S;
     lds<A> *L;         // LDS tile (2^k amplitudes, swizzled positions)
     uint32_t lbase;    // LDS byte address of L (0, or the second buffer)
-    lds<uint32_t> *hi_off;  // LDS: global offset of local index bits >= 4
+    lds<uint32_t> *hi_off;  // LDS: global offset of local index bits >= kCoalesceQ
     lds<int16_t> *dec; // LDS: decided outcome of each op of the pass
     lds<int> *cnt;     // LDS: 16 x kWG outcome counters (splits); aliases the tile
                        // of a streamed state (free between sweeps)
@@ -736,11 +736,11 @@ struct TileIO {
     __device__ void setup(Ctx<R> &c)
     {
         const uint32_t l = (uint32_t)c.tid * V;
-        gt = (c.hi_off[l >> 4] + (l & 15u)) / V;
+        gt = (c.hi_off[l >> kCoalesceQ] + (l & kRunMask)) / V;
         pt = c.at(l) * (uint32_t)sizeof(A);
 #pragma unroll
         for (int j = 0; j < LNC; ++j)
-            gb[j] = __builtin_amdgcn_readfirstlane(c.hi_off[(uint32_t)((kWG * V) << j) >> 4] / V);
+            gb[j] = __builtin_amdgcn_readfirstlane(c.hi_off[(uint32_t)((kWG * V) << j) >> kCoalesceQ] / V);
     }
     // the deposit is linear over disjoint bits, so offsets of chunk u
     // combine from per-bit offsets without a table lookup per tile
@@ -802,11 +802,11 @@ struct TileIO {
     {
         tid = (uint32_t)c.tid;
         const uint32_t l = c.at((uint32_t)c.tid * V);
-        lt = (c.hi_off[l >> 4] + (l & 15u)) / V;
+        lt = (c.hi_off[l >> kCoalesceQ] + (l & kRunMask)) / V;
 #pragma unroll
         for (int j = 0; j < LNC; ++j) {
             const uint32_t m = c.at((uint32_t)((kWG * V) << j));
-            lb[j] = __builtin_amdgcn_readfirstlane((c.hi_off[m >> 4] + (m & 15u)) / V);
+            lb[j] = __builtin_amdgcn_readfirstlane((c.hi_off[m >> kCoalesceQ] + (m & kRunMask)) / V);
         }
     }
     __device__ __forceinline__ uint32_t lu(int u) const
@@ -1156,7 +1156,7 @@ __device__ void load_tile(Ctx<R> &c, const gbl<typename V2<R>::T> *G, uint64_t b
     if (fresh) {
         for (uint32_t ch = c.tid; ch < nch; ch += kWG) {
             const uint32_t l = ch * V;
-            const uint64_t g = base + c.hi_off[l >> 4] + (l & 15u);
+            const uint64_t g = base + c.hi_off[l >> kCoalesceQ] + (l & kRunMask);
 #pragma unroll
             for (uint32_t v = 0; v < V; ++v) {
                 A z;
@@ -1171,7 +1171,7 @@ __device__ void load_tile(Ctx<R> &c, const gbl<typename V2<R>::T> *G, uint64_t b
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const uint32_t l = (ch0 + u * kWG) * V;
-                x[u] = *(const gbl<u32x4> *)(G + base + c.hi_off[l >> 4] + (l & 15u));
+                x[u] = *(const gbl<u32x4> *)(G + base + c.hi_off[l >> kCoalesceQ] + (l & kRunMask));
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -1182,7 +1182,7 @@ __device__ void load_tile(Ctx<R> &c, const gbl<typename V2<R>::T> *G, uint64_t b
     } else {
         for (uint32_t ch = c.tid; ch < nch; ch += kWG) {
             const uint32_t l = ch * V;
-            *(lds<u32x4> *)(c.L + c.at(l)) = *(const gbl<u32x4> *)(G + base + c.hi_off[l >> 4] + (l & 15u));
+            *(lds<u32x4> *)(c.L + c.at(l)) = *(const gbl<u32x4> *)(G + base + c.hi_off[l >> kCoalesceQ] + (l & kRunMask));
         }
     }
     __syncthreads();
@@ -1195,7 +1195,7 @@ __device__ void store_tile(Ctx<R> &c, gbl<typename V2<R>::T> *G, uint64_t base)
     constexpr uint32_t V = 16 / sizeof(A);
     for (uint32_t ch = c.tid; ch < c.tsize / V; ch += kWG) {
         const uint32_t l = ch * V;
-        const uint64_t g = base + c.hi_off[l >> 4] + (l & 15u);
+        const uint64_t g = base + c.hi_off[l >> kCoalesceQ] + (l & kRunMask);
         *(gbl<u32x4> *)(G + g) = *(const lds<u32x4> *)(c.L + c.at(l));
     }
     __syncthreads();
@@ -1948,7 +1948,7 @@ __device__ __noinline__ void dump_state(Ctx<R> &c, const PassInfo &pi)
         const uint64_t base = tile_base<R>(pi, n, k, t);
         load_tile(c, G, base, S.fresh != 0);
         for (uint32_t l = c.tid; l < c.tsize; l += kWG) {
-            const uint64_t g = base + c.hi_off[l >> 4] + (l & 15u);
+            const uint64_t g = base + c.hi_off[l >> kCoalesceQ] + (l & kRunMask);
             const A v = c.L[l];
             out[g] = make_double2((double)v.x * f, (double)v.y * f);
         }
@@ -1972,8 +1972,15 @@ __device__ __noinline__ void maybe_dump(Ctx<R> &c, int at_op)
     dump_state(c, P.passes[pidx]);
 }
 
+// Register budget: configurations whose tile lets two workgroups share a
+// CU are held to two waves per SIMD (256 VGPRs), so one workgroup can
+// stream its tile while the other computes.
 template <class R, int NR>
-__global__ void __launch_bounds__(kWG) exec_kernel(ExecParams P)
+constexpr int exec_waves() { return (NR > 0 && NR * (int)sizeof(R) * 2 <= 256) ? 2 : 1; }
+
+template <class R, int NR>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(exec_waves<R, NR>())))
+exec_kernel(ExecParams P)
 {
     using A = typename V2<R>::T;
     extern __shared__ __align__(16) unsigned char smem[];

@@ -15,6 +15,7 @@ constexpr int kMaxKraus = 8;         // matrices per Kraus channel
 constexpr int kMaxMeasQ = 4;         // qubits of a non-terminal measure
 constexpr int kMaxRed = 1 + 16;      // norm + up to 16 outcome sums
 constexpr int kCoalesceQ = 4;        // low qubits always inside a tile
+constexpr uint32_t kRunMask = (1u << kCoalesceQ) - 1;  // contiguous run of a tile in HBM
 constexpr int kMaxTileQ = 14;
 
 // Device op kinds (after noise-site expansion).
