@@ -210,7 +210,9 @@ struct WgShared {
 };
 
 // Register micro-op built at plan time (fused 2x2 matrices, permutations).
-enum UKind : uint8_t { UK_MAT1 = 1, UK_DIAG1 = 2, UK_CX = 3, UK_CZ = 4, UK_SWAP = 5 };
+// UK_MAT1R: a 2x2 matrix whose top-left entry is real (a U3 gate, alone or
+// with diagonal noise factors), two multiplications fewer per pair
+enum UKind : uint8_t { UK_MAT1 = 1, UK_DIAG1 = 2, UK_CX = 3, UK_CZ = 4, UK_SWAP = 5, UK_MAT1R = 6 };
 struct UOp {
     uint8_t kind, j0, j1, pad;
     uint16_t mat, pad2;
@@ -564,6 +566,29 @@ __device__ __forceinline__ void r_mat1(A (&v)[NR], const R (&m)[8])
     }
 }
 
+// Same as r_mat1 for a real top-left entry m[0] (m[1] == 0): the products
+// are the ones r_mat1 forms, without the terms that multiply by zero.
+template <int J, class A, class R, int NR>
+__device__ __forceinline__ void r_mat1r(A (&v)[NR], const R (&m)[8])
+{
+    if constexpr ((1 << J) < NR) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (i & (1 << J)) continue;
+            const int i1 = i | (1 << J);
+            const A a = v[i], b = v[i1];
+            A o0;
+            o0.x = m[0] * a.x;
+            o0.y = m[0] * a.y;
+            o0 = cmac<A, R>(o0, m[2], m[3], b);
+            A o1 = cmul<A, R>(m[4], m[5], a);
+            o1 = cmac<A, R>(o1, m[6], m[7], b);
+            v[i] = o0;
+            v[i1] = o1;
+        }
+    }
+}
+
 template <int J, class A, class R, int NR>
 __device__ __forceinline__ void r_diag1(A (&v)[NR], const R (&m)[8])
 {
@@ -618,11 +643,12 @@ __device__ __forceinline__ void r_swap(A (&v)[NR])
 }
 
 template <class A, class R, int NR>
-__device__ __forceinline__ void d_mat1(A (&v)[NR], int j, const R (&m)[8], bool diag)
+__device__ __forceinline__ void d_mat1(A (&v)[NR], int j, const R (&m)[8], int kind)
 {
 #define SVB_M1(J)                                   \
     case J:                                         \
-        if (diag) r_diag1<J, A, R, NR>(v, m);       \
+        if (kind == UK_MAT1R) r_mat1r<J, A, R, NR>(v, m);  \
+        else if (kind == UK_DIAG1) r_diag1<J, A, R, NR>(v, m); \
         else r_mat1<J, A, R, NR>(v, m);             \
         break;
     switch (j) { SVB_M1(0) SVB_M1(1) SVB_M1(2) SVB_M1(3) SVB_M1(4) SVB_M1(5) default: break; }
@@ -697,11 +723,11 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
     const lds<R> *mats = (const lds<R> *)(size_t)h.mats;
     for (int q = 0; q < count; ++q) {
         const UOp u = get_uop(uops + first + q);
-        if (u.kind == UK_MAT1 || u.kind == UK_DIAG1) {
+        if (u.kind == UK_MAT1 || u.kind == UK_DIAG1 || u.kind == UK_MAT1R) {
             R m[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) m[e] = uni(mats[u.mat * 8 + e]);
-            d_mat1<A, R, NR>(v, u.j0, m, u.kind == UK_DIAG1);
+            d_mat1<A, R, NR>(v, u.j0, m, u.kind);
         } else {
             d_two<A, NR>(v, u.kind, u.j0, u.j1);
         }
@@ -719,81 +745,21 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
 // is a scalar-base load/store with a precomputed vector offset.
 template <class R, int NR>
 struct TileIO {
-    // Chunk u of thread t holds tile index l = (u*kWG + t)*V. Both the
-    // global offset (hi_off is a bit deposit) and the LDS position (the
-    // swizzle is an XOR of bit fields) split into a per-thread part and a
-    // per-u part that is the same for every thread of the workgroup.
+    // Copy chunk u of thread t is LDS byte (u*kWG + t)*16 of a tile buffer.
+    // Its global offset (hi_off is a bit deposit, the swizzle an XOR of bit
+    // fields) splits into a per-thread part and a per-u part that is the
+    // same for every thread of the workgroup.
     using A = typename V2<R>::T;
     static constexpr int V = 16 / sizeof(A);
     static constexpr int NC = NR / V;
     static constexpr int LNC = NC >= 64 ? 6 : NC >= 32 ? 5 : NC >= 16 ? 4 : NC >= 8 ? 3 : NC >= 4 ? 2 : NC >= 2 ? 1 : 0;
-    // Global offsets are kept in 16-byte chunks (the size of one copy),
-    // so 32 bits reach every byte of a state of up to 64 GiB.
-    uint32_t gt;        // per-thread global chunk offset
-    uint32_t pt;        // per-thread LDS byte position
-    uint32_t gb[LNC + 1];  // global chunk offset of chunk-index bit j (uniform)
-
-    __device__ void setup(Ctx<R> &c)
-    {
-        const uint32_t l = (uint32_t)c.tid * V;
-        gt = (c.hi_off[l >> kCoalesceQ] + (l & kRunMask)) / V;
-        pt = c.at(l) * (uint32_t)sizeof(A);
-#pragma unroll
-        for (int j = 0; j < LNC; ++j)
-            gb[j] = __builtin_amdgcn_readfirstlane(c.hi_off[(uint32_t)((kWG * V) << j) >> kCoalesceQ] / V);
-    }
-    // the deposit is linear over disjoint bits, so offsets of chunk u
-    // combine from per-bit offsets without a table lookup per tile
-    __device__ __forceinline__ uint32_t gu(Ctx<R> &, int u) const
-    {
-        uint32_t g = 0;
-#pragma unroll
-        for (int j = 0; j < LNC; ++j)
-            if (u & (1 << j)) g ^= gb[j];
-        return g;
-    }
-    __device__ __forceinline__ uint32_t pu(Ctx<R> &c, int u) const
-    {
-        return __builtin_amdgcn_readfirstlane(c.at((uint32_t)(u * kWG * V)) * (uint32_t)sizeof(A));
-    }
-
-    __device__ void load(Ctx<R> &c, const gbl<A> *Gt, uint64_t base, bool fresh)
-    {
-        if (fresh) {
-#pragma unroll
-            for (int u = 0; u < NC; ++u) {
-                const uint64_t g = base + (uint64_t)(gt + gu(c, u)) * V;
-#pragma unroll
-                for (int e = 0; e < V; ++e) {
-                    A z;
-                    z.x = (g + e == 0) ? (R)1 : (R)0;
-                    z.y = 0;
-                    *(lds<A> *)(size_t)((pt ^ pu(c, u)) + e * sizeof(A)) = z;
-                }
-            }
-        } else {
-            const gbl<u32x4> *G16 = (const gbl<u32x4> *)(Gt + base);
-            constexpr int BATCH = NC < 16 ? NC : 16;
-#pragma unroll
-            for (int u0 = 0; u0 < NC; u0 += BATCH) {
-                u32x4 x[BATCH];
-#pragma unroll
-                for (int u = 0; u < BATCH; ++u)
-                    x[u] = G16[gu(c, u0 + u) + gt];
-#pragma unroll
-                for (int u = 0; u < BATCH; ++u)
-                    *(lds<u32x4> *)(size_t)(pt ^ pu(c, u0 + u)) = x[u];
-            }
-        }
-        __syncthreads();
-    }
-
-    // ---- double-buffered streaming: LDS is filled and drained in linear
-    // order (16 bytes per lane, a wave covers 1 KB), so the next tile can
-    // be fetched straight into LDS with no registers while this one
-    // computes. LDS byte (u*kWG + t)*16 of a buffer holds tile index
-    // at(p), p = (u*kWG + t)*V; at() is its own inverse, so the amplitude
-    // of tile index l still sits at position at(l).
+    // LDS is filled and drained in linear order (16 bytes per lane, a wave
+    // covers 1 KB), so a tile is fetched straight into LDS with no register
+    // staging. LDS byte (u*kWG + t)*16 of a buffer holds tile index at(p),
+    // p = (u*kWG + t)*V; at() is its own inverse, so the amplitude of tile
+    // index l sits at position at(l), where the register groups expect it.
+    // Global offsets are kept in 16-byte chunks (the size of one copy), so
+    // 32 bits reach every byte of a state of up to 64 GiB.
     uint32_t lt;          // per-thread global chunk offset of linear chunk 0
     uint32_t lb[LNC + 1]; // global chunk offset of linear chunk-index bit j (uniform)
     uint32_t tid;
@@ -829,6 +795,21 @@ struct TileIO {
                                              (lds<void> *)(size_t)(wb + (uint32_t)u * kWG * 16u),
                                              16, 0, 0);
     }
+    // The tile of the virtual |0..0> state: zeros, and amplitude 1 at tile
+    // index 0 (LDS position 0) of the tile that holds global index 0.
+    __device__ void zero(bool holds_origin) const
+    {
+        const uint32_t p0 = tid * 16u;
+        u32x4 z = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int u = 0; u < NC; ++u) *(lds<u32x4> *)(size_t)(p0 + (uint32_t)u * kWG * 16u) = z;
+        if (holds_origin && tid == 0) {
+            A one;
+            one.x = (R)1;
+            one.y = (R)0;
+            *(lds<A> *)(size_t)0 = one;
+        }
+    }
     __device__ void store_linear(gbl<A> *Gt, uint64_t base, uint32_t buf) const
     {
         gbl<u32x4> *G16 = (gbl<u32x4> *)(Gt + base);
@@ -839,14 +820,6 @@ struct TileIO {
                 *(const lds<u32x4> *)(size_t)(p0 + (uint32_t)u * kWG * 16u);
     }
 
-    __device__ void store(Ctx<R> &c, gbl<A> *Gt, uint64_t base)
-    {
-        gbl<u32x4> *G16 = (gbl<u32x4> *)(Gt + base);
-#pragma unroll
-        for (int u = 0; u < NC; ++u)
-            G16[gu(c, u) + gt] = *(const lds<u32x4> *)(size_t)(pt ^ pu(c, u));
-        __syncthreads();
-    }
 };
 
 // ---- plan-time fusion (thread 0): per register bit a pending FP64 2x2
@@ -882,7 +855,7 @@ __device__ bool fuse_flush(Ctx<R> &c, int j, uint32_t &pend_set, int &nu, int &n
     const bool diag = pm[2] == 0.0 && pm[3] == 0.0 && pm[4] == 0.0 && pm[5] == 0.0;
     for (int e = 0; e < 8; ++e) c.mats[nm * 8 + e] = (R)pm[e];
     UOp u;
-    u.kind = diag ? UK_DIAG1 : UK_MAT1;
+    u.kind = diag ? UK_DIAG1 : (pm[1] == 0.0 ? UK_MAT1R : UK_MAT1);
     u.j0 = (uint8_t)j;
     u.j1 = 0;
     u.pad = 0;
@@ -890,7 +863,7 @@ __device__ bool fuse_flush(Ctx<R> &c, int j, uint32_t &pend_set, int &nu, int &n
     u.pad2 = 0;
     put_uop(c.uops + nu++, u);
     ++nm;
-    flops += diag ? 6 : 14;
+    flops += diag ? 6 : (pm[1] == 0.0 ? 12 : 14);
     return true;
 }
 
@@ -1651,13 +1624,13 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
                 h.tid = c.tid;
                 const cst<GroupInfo> *groups = to_const(P.groups);
                 const cst<PassInfo> &pc = *to_const(&pi);
+                TileIO<R, NR> io;
+                io.setup_linear(c);
+                // nothing below may read private memory: such a load would
+                // wait for the tile copy in flight
+                const uint32_t nt = uni(1u << (n - k));
                 if (P.nbuf == 2 && !fresh) {
-                    TileIO<R, NR> io;
-                    io.setup_linear(c);
-                    // nothing below may read private memory: such a load
-                    // would wait for the tile copy in flight
                     const uint32_t tb = uni((1u << k) * (uint32_t)sizeof(A));  // buffer 1 starts here
-                    const uint32_t nt = uni(1u << (n - k));
                     lds<A> *const L0 = c.L;
                     io.issue(G, tile_base_c(pc, n, k, 0), 0);
                     for (uint32_t t = 0; t < nt; ++t) {
@@ -1674,19 +1647,23 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
                     }
                     c.lbase = 0;
                     c.L = L0;
-                    wait_vm();
-                    __syncthreads();
                 } else {
-                    TileIO<R, NR> io;
-                    io.setup(c);
-                    for (uint32_t t = 0; t < c.n_tiles; ++t) {
+                    // one buffer, filled by asynchronous global->LDS copies
+                    // (no register staging) and drained in linear order
+                    for (uint32_t t = 0; t < nt; ++t) {
                         const uint64_t base = tile_base_c(pc, n, k, t);
-                        io.load(c, G, base, fresh);
+                        if (fresh) io.zero(base == 0);
+                        else io.issue(G, base, 0);
+                        wait_vm();
+                        __syncthreads();
                         if (grp) run_groups<R, NR>(c, h, groups);
                         if (want_reduce) reduce_tile(c, rop, acc);
-                        if (has_ops) io.store(c, G, base);
+                        if (has_ops) io.store_linear(G, base, 0);
+                        lds_sync();  // the buffer is read out before the next copy lands
                     }
                 }
+                wait_vm();  // the next pass reads what these stores write
+                __syncthreads();
             }
         }
         if (!(NR > 0 && P.use_groups)) {
