@@ -48,6 +48,16 @@ template <class T> using gbl = __attribute__((address_space(1))) T;
 // address space: uniform reads become scalar loads, which leave the vector
 // memory counter to the tile copies in flight
 template <class T> using cst = __attribute__((address_space(4))) T;
+// a pointer every lane holds the same value of, made uniform (scalar)
+template <class T>
+__device__ __forceinline__ gbl<T> *uni_ptr(gbl<T> *p)
+{
+    const uint64_t a = (uint64_t)p;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (gbl<T> *)(lo | (hi << 32));
+}
+
 template <class T>
 __device__ __forceinline__ const cst<T> *to_const(const T *p)
 {
@@ -676,6 +686,7 @@ __device__ __forceinline__ void d_two(A (&v)[NR], int kind, int c, int t)
 struct Hot {
     uint32_t ug, uops, mats;  // LDS byte addresses of the pass's groups, micro-ops, matrices
     uint32_t lbase;           // LDS byte address of the current tile buffer
+    uint32_t hi;              // LDS byte address of the tile's global-offset table
     uint32_t swm;             // swizzle mask
     int n_ug, k, tid;
     __device__ __forceinline__ uint32_t at(uint32_t i) const
@@ -684,10 +695,13 @@ struct Hot {
     }
 };
 
+template <class R, int NR> struct Direct;
+
 // Gather the thread's NR amplitudes of group gi from LDS, run the group's
-// micro-ops in registers, scatter back.
-template <class R, int NR>
-__device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi, int first, int count)
+// micro-ops in registers, scatter back (to LDS, or with DIRECT to HBM).
+template <class R, int NR, bool DIRECT>
+__device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi, int first, int count,
+                                          const Direct<R, NR> &d)
 {
     using A = typename V2<R>::T;
     constexpr int RB = NR == 64 ? 6 : NR == 32 ? 5 : NR == 16 ? 4 : 3;
@@ -719,6 +733,10 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
     A v[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) v[i] = *(const lds<A> *)(size_t)(pb8 ^ K[i]);
+    if constexpr (DIRECT) {
+        lds_sync();  // every thread has its amplitudes: the buffer is free
+        if (d.issue_next) d.io.issue(d.state, d.next_base, 0);
+    }
     const lds<UOp> *uops = (const lds<UOp> *)(size_t)h.uops;
     const lds<R> *mats = (const lds<R> *)(size_t)h.mats;
     for (int q = 0; q < count; ++q) {
@@ -732,12 +750,38 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
             d_two<A, NR>(v, u.kind, u.j0, u.j1);
         }
     }
-    // recompute the addresses rather than keep NR of them live
-    uint32_t pw = pb8;
-    asm volatile("" : "+v"(pw));
+    if constexpr (DIRECT) {
+        // global amplitude offset of tile index x: hi[x >> kCoalesceQ] + (x & kRunMask),
+        // a bit deposit, so the thread part and the register parts add
+        const lds<uint32_t> *hi = (const lds<uint32_t> *)(size_t)h.hi;
+        const uint32_t gbase = hi[base >> kCoalesceQ] + (base & kRunMask);
+        uint32_t ge[RB];
 #pragma unroll
-    for (int i = 0; i < NR; ++i) *(lds<A> *)(size_t)(pw ^ K[i]) = v[i];
-    lds_sync();
+        for (int j = 0; j < RB; ++j) {
+            const uint32_t x = 1u << ((gpw[j >> 2] >> (8 * (j & 3))) & 0xffu);
+            ge[j] = __builtin_amdgcn_readfirstlane(hi[x >> kCoalesceQ] + (x & kRunMask));
+        }
+        // uniform part in the scalar base, thread part as the 32-bit vector
+        // offset: one address register for all NR stores
+        const uint32_t voff = gbase * (uint32_t)sizeof(A);
+        uint32_t G[NR];
+        G[0] = 0;
+#pragma unroll
+        for (int i = 1; i < NR; ++i) G[i] = G[i & (i - 1)] + ge[__builtin_ctz(i)];
+        gbl<A> *const tile = uni_ptr(d.tile);
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            gbl<unsigned char> *sb = (gbl<unsigned char> *)(tile + G[i]);
+            *(gbl<A> *)(sb + voff) = v[i];
+        }
+    } else {
+        // recompute the addresses rather than keep NR of them live
+        uint32_t pw = pb8;
+        asm volatile("" : "+v"(pw));
+#pragma unroll
+        for (int i = 0; i < NR; ++i) *(lds<A> *)(size_t)(pw ^ K[i]) = v[i];
+        lds_sync();
+    }
 }
 
 // Per-pass chunk offsets of a thread for streamed tile copies: global byte
@@ -820,6 +864,20 @@ struct TileIO {
                 *(const lds<u32x4> *)(size_t)(p0 + (uint32_t)u * kWG * 16u);
     }
 
+};
+
+// The last register group of a tile may write its results straight from
+// registers to the state in HBM. The tile buffer is then free once the
+// group has gathered, and the next tile's copy into it is issued before
+// the group computes. Passed by value through inlined code: nothing here
+// may live in private memory.
+template <class R, int NR>
+struct Direct {
+    gbl<typename V2<R>::T> *tile;  // the state at this tile's base
+    const gbl<typename V2<R>::T> *state;
+    uint64_t next_base;            // the next tile's base, if issue_next
+    bool issue_next;
+    TileIO<R, NR> io;
 };
 
 // ---- plan-time fusion (thread 0): per register bit a pending FP64 2x2
@@ -1573,19 +1631,31 @@ __device__ __noinline__ void run_fallback(Ctx<R> &c, int a, int b)
     }
 }
 
-// The pass's groups on the current tile, in order.
+// The pass's groups on the current tile, in order. With d, a last group
+// that runs in registers stores the tile to HBM itself (returns true).
 template <class R, int NR>
-__device__ __forceinline__ void run_groups(Ctx<R> &c, const Hot &h, const cst<GroupInfo> *groups)
+__device__ __forceinline__ bool run_groups(Ctx<R> &c, const Hot &h, const cst<GroupInfo> *groups,
+                                           bool direct, const Direct<R, NR> &d)
 {
+    bool stored = false;
     for (int u = 0; u < h.n_ug; ++u) {
         const lds<UGroup> &gl = ((const lds<UGroup> *)(size_t)h.ug)[u];
         const int gidx = (int)uni((uint32_t)gl.gidx);
         const int a = (int)uni((uint32_t)gl.a);
         const int b = (int)uni((uint32_t)gl.b);
         const int fb = (int)uni((uint32_t)gl.fallback);
-        if (fb) run_fallback<R>(c, a, b);
-        else if constexpr (NR > 0) run_group<R, NR>(h, groups[gidx], a, b);
+        if (fb) {
+            run_fallback<R>(c, a, b);
+        } else if constexpr (NR > 0) {
+            if (direct && u == h.n_ug - 1) {
+                run_group<R, NR, true>(h, groups[gidx], a, b, d);
+                stored = true;
+            } else {
+                run_group<R, NR, false>(h, groups[gidx], a, b, d);
+            }
+        }
     }
+    return stored;
 }
 
 template <class R, int NR>
@@ -1618,6 +1688,7 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
                 h.uops = (uint32_t)(size_t)c.uops;
                 h.mats = (uint32_t)(size_t)c.mats;
                 h.lbase = 0;
+                h.hi = (uint32_t)(size_t)c.hi_off;
                 h.swm = uni(c.swm);
                 h.n_ug = (int)uni((uint32_t)S.n_ug);
                 h.k = k;
@@ -1641,7 +1712,7 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
                         h.lbase = cur;
                         c.lbase = cur;  // cold paths (fallback groups, reductions) use c.L
                         c.L = (lds<A> *)((lds<unsigned char> *)L0 + cur);
-                        if (grp) run_groups<R, NR>(c, h, groups);
+                        if (grp) run_groups<R, NR>(c, h, groups, false, Direct<R, NR>{G, G, 0, false, io});
                         if (want_reduce) reduce_tile(c, rop, acc);
                         if (has_ops) io.store_linear(G, tile_base_c(pc, n, k, t), cur);
                     }
@@ -1649,17 +1720,28 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
                     c.L = L0;
                 } else {
                     // one buffer, filled by asynchronous global->LDS copies
-                    // (no register staging) and drained in linear order
+                    // (no register staging) and drained in linear order, or
+                    // by the last register group straight from registers
+                    const bool direct = grp && !want_reduce;
+                    if (!fresh) io.issue(G, tile_base_c(pc, n, k, 0), 0);
                     for (uint32_t t = 0; t < nt; ++t) {
                         const uint64_t base = tile_base_c(pc, n, k, t);
+                        const bool more = !fresh && t + 1 < nt;
+                        const uint64_t next = more ? tile_base_c(pc, n, k, t + 1) : 0;
                         if (fresh) io.zero(base == 0);
-                        else io.issue(G, base, 0);
                         wait_vm();
                         __syncthreads();
-                        if (grp) run_groups<R, NR>(c, h, groups);
+                        bool stored = false;
+                        if (grp) {
+                            stored = run_groups<R, NR>(c, h, groups, direct,
+                                                       Direct<R, NR>{G + base, G, next, more, io});
+                        }
                         if (want_reduce) reduce_tile(c, rop, acc);
-                        if (has_ops) io.store_linear(G, base, 0);
-                        lds_sync();  // the buffer is read out before the next copy lands
+                        if (!stored) {
+                            if (has_ops) io.store_linear(G, base, 0);
+                            lds_sync();  // the buffer is read out before the next copy lands
+                            if (more) io.issue(G, next, 0);
+                        }
                     }
                 }
                 wait_vm();  // the next pass reads what these stores write
