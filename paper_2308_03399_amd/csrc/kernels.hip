@@ -525,6 +525,7 @@ __device__ __noinline__ void apply_op(Ctx<R> &c, const DevOp &op, int d, double 
     }
     case DK_KRAUS: {
         const DevRule &ru = P.rules[op.rule];
+        if (((ru.scalar_mask >> d) & 1u) && s == 1.0) break;  // c * I: norm only
         const uint32_t dim = 1u << ru.nq;
         const double *m = P.pool + ru.mats + (size_t)d * dim * dim * 2;
         if (ru.nq == 1) {
@@ -981,6 +982,8 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
                 break;
             case DK_KRAUS: {
                 const DevRule &ru = P.rules[op.rule];
+                // c * I: the state is kept unnormalised anyway
+                if (((ru.scalar_mask >> d) & 1u) && sc == 1.0) break;
                 fuse_factor(c, op.rb[0], P.pool + ru.mats + (size_t)d * 8, sc, pend_set);
                 break;
             }
@@ -1544,7 +1547,7 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
             }
             if (u < ru.lam_min0 && nlb * ru.lam_min0 >= lb_floor) {
                 if (tid == 0) c.dec[j - start] = 0;
-                nlb *= ru.lam_min0;
+                if (!(ru.scalar_mask & 1u)) nlb *= ru.lam_min0;
                 ++j;
                 continue;
             }
@@ -1586,7 +1589,7 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
         }
         if (!anyhigh && nlb * ru.lam_min0 >= lb_floor) {
             if (tid == 0) c.dec[j - start] = 0;
-            nlb *= ru.lam_min0;
+            if (!(ru.scalar_mask & 1u)) nlb *= ru.lam_min0;
             ++j;
             continue;
         }

@@ -11,7 +11,7 @@ constexpr int kMaxPassOps = 512;     // ops applied in one tile sweep
 constexpr int kMaxPassGroups = 64;   // register groups in one sweep
 constexpr int kMaxPassUops = 384;    // register micro-ops in one sweep
 constexpr int kPassMatBytes = 6144;  // LDS bytes for the fused 2x2 matrices of one sweep
-constexpr int kMaxKraus = 8;         // matrices per Kraus channel
+constexpr int kMaxKraus = 16;        // matrices per Kraus channel
 constexpr int kMaxMeasQ = 4;         // qubits of a non-terminal measure
 constexpr int kMaxRed = 1 + 16;      // norm + up to 16 outcome sums
 constexpr int kCoalesceQ = 4;        // low qubits always inside a tile
@@ -77,7 +77,7 @@ struct DevRule {
     uint32_t zcode[16];  // Pauli term: bit t set if Z or Y on gate qubit t
     uint32_t ny[16];     // Pauli term: number of Y
     uint32_t ident_mask; // Pauli: bit j set if term j is the identity
-    uint32_t pad2;
+    uint32_t scalar_mask;// Kraus: bit j set if matrix j is a multiple of the identity
 };
 
 struct PassInfo {

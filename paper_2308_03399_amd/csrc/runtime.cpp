@@ -725,6 +725,16 @@ static void rule_dev(const Rule &R, std::vector<double> &pool, DevRule &d)
                 }
         }
         d.diag_mm = diag;
+        // matrices that are c * I: choosing one leaves the state's direction
+        // unchanged (only its norm), which every later decision divides out
+        for (size_t j = 0; j < R.mats.size(); ++j) {
+            const auto &m = R.mats[j];
+            bool sc = true;
+            for (int a = 0; a < dd && sc; ++a)
+                for (int c = 0; c < dd && sc; ++c)
+                    sc = (a == c) ? (m[a * dd + c] == m[0]) : (m[a * dd + c] == cd(0, 0));
+            if (sc) d.scalar_mask |= 1u << j;
+        }
         double lam;
         if (dd == 2) {
             const double a = M0[0].real(), c = M0[3].real();

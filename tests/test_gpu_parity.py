@@ -227,3 +227,21 @@ def test_largest_state_offsets_beyond_32_bits():
     _, psi = oracle.run(circ, noise, [1], seed=3, stop_at=len_expanded(circ, noise),
                         want_state=True)
     assert np.max(np.abs(got["state"] - psi)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# The paper's QFT workload (Sec. V): H, phase and CX with depolarizing noise
+# as a Pauli channel or as the equivalent Kraus list (16 matrices for CX)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form,mode,n,tile", [("pauli", "batch", 9, 0), ("kraus", "batch", 9, 0),
+                                              ("kraus", "branch", 9, 0), ("kraus", "batch", 14, 12),
+                                              ("pauli", "branch", 14, 12), ("kraus", "plain", 9, 0)])
+def test_qft_workload_matches_oracle(form, mode, n, tile):
+    circ = W.qft(n, prepare=5)
+    noise = W.qft_noise(0.05, form)
+    shots = 96 if mode != "plain" else 24
+    say(f"case qft form={form} mode={mode} n={n} tile={tile}")
+    opts = {"tile_qubits": tile} if tile else {}
+    got = gpu_run(circ, noise, shots, dtype="c128", mode=mode, seed=11, **opts)
+    exp = oracle_memory(circ, noise, shots, seed=11)
+    assert mismatches(got["memory"], exp) == 0

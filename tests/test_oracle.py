@@ -329,3 +329,42 @@ def test_oracle_sample_mismatch_detects_wrong_channel_order():
     assert dm.tvd(da, db) > 0.1
     mem = oracle.run(circ, a, 20000, seed=0)
     _sample_check(mem, da, 20000)
+
+
+@pytest.mark.parametrize("x", [0, 1, 6, 19])
+def test_qft_workload_is_the_discrete_fourier_transform(x):
+    # the decomposed textbook QFT (H, phase, CX, three-CX swaps) maps |x>
+    # to sum_y exp(2 pi i x y / N) |y> / sqrt(N): numpy's FFT is the check
+    n = 5
+    circ = W.qft(n, prepare=x, measure_all=False)
+    noise = W.noise_model([])
+    psi = _state(circ, noise, stop_at=len(dm.expand(circ, noise)))
+    N = 1 << n
+    expect = np.fft.ifft(np.eye(N)[x]) * math.sqrt(N)   # exp(+2 pi i x y / N) / sqrt(N)
+    assert np.max(np.abs(psi - expect)) < 1e-14
+
+
+def test_depolarizing_kraus_form_equals_pauli_form():
+    # the same channel given as a Kraus list (Sec. III-B) reaches the same
+    # exact distribution, and the oracle's Kraus selection samples it
+    p, k = 0.05, 7
+    ops = [{"kind": "h", "qubits": [0]}, {"kind": "cx", "qubits": [0, 1]}]
+    ops += [{"kind": "id", "qubits": [0]}] * k + [{"kind": "swap", "qubits": [0, 1]}] * 2
+    ops += [{"kind": "measure", "qubits": [0, 1], "clbits": [0, 1]}]
+    circ = {"n_qubits": 2, "n_clbits": 2, "ops": ops}
+    rules_p = [W.rule(["id"], W.depolarizing_pauli(p, 1)), W.rule(["swap"], W.depolarizing_pauli(p, 2))]
+    rules_k = [W.rule(["id"], W.depolarizing_kraus(p, 1)), W.rule(["swap"], W.depolarizing_kraus(p, 2))]
+    dp = dm.creg_distribution_dm(circ, W.noise_model(rules_p))
+    dk = dm.creg_distribution_dm(circ, W.noise_model(rules_k))
+    for key in range(4):
+        assert abs(dp.get(key, 0.0) - dk.get(key, 0.0)) < 1e-13
+    # one qubit, closed form
+    one = {"n_qubits": 1, "n_clbits": 1,
+           "ops": [{"kind": "id", "qubits": [0]}] * k + [{"kind": "measure", "qubits": [0], "clbits": [0]}]}
+    nk = W.noise_model([W.rule(["id"], W.depolarizing_kraus(p, 1))])
+    d1 = dm.creg_distribution_dm(one, nk)
+    assert abs(d1[1] - (1 - (1 - p) ** k) / 2) < 1e-13
+    mem = oracle.run(one, nk, 40000, seed=9)
+    _sample_check(mem, d1, 40000)
+    mem2 = oracle.run(circ, W.noise_model(rules_k), 20000, seed=4)
+    _sample_check(mem2, dk, 20000)

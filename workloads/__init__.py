@@ -85,6 +85,63 @@ def amplitude_damping_kraus(gamma: float) -> Dict:
     return {"type": "kraus", "nq": 1, "mats": [k0, k1]}
 
 
+def depolarizing_kraus(p: float, nq: int) -> Dict:
+    """Kraus form of the same n-qubit depolarizing channel as
+    depolarizing_pauli: sqrt(prob) times each Pauli string, in the same
+    order (any channel, Pauli ones included, can be given as a Kraus list,
+    Sec. III-B). Matrix index bit t is the gate's qubit t."""
+    single = {"I": np.eye(2), "X": np.array([[0, 1], [1, 0]]),
+              "Y": np.array([[0, -1j], [1j, 0]]), "Z": np.diag([1, -1])}
+    pc = depolarizing_pauli(p, nq)
+    mats = []
+    for prob, s in zip(pc["probs"], pc["paulis"]):
+        m = np.ones((1, 1), dtype=complex)
+        for ch in s:                      # qubit 0 first: it ends up least significant
+            m = np.kron(single[ch], m)
+        mats.append((math.sqrt(prob) * m).tolist())
+    return {"type": "kraus", "nq": nq, "mats": mats}
+
+
+def qft(n_qubits: int, prepare: int = 0, measure_all: bool = True) -> Dict:
+    """Textbook quantum Fourier transform (Sec. V workload) written over the
+    gate set the paper's noise model names: H, phase (U3(0, 0, lam)) and CX.
+    Each controlled phase CP(lam) on (a, b) is p(lam/2) a, CX(a, b),
+    p(-lam/2) b, CX(a, b), p(lam/2) b; the final qubit reversal is three CX
+    per swap. `prepare` sets the input basis state with X gates first."""
+    ops = []
+    for q in range(n_qubits):
+        if (prepare >> q) & 1:
+            ops.append({"kind": "x", "qubits": [q]})
+
+    def phase(q, lam):
+        ops.append({"kind": "u3", "qubits": [q], "params": [0.0, 0.0, lam]})
+
+    for j in reversed(range(n_qubits)):
+        ops.append({"kind": "h", "qubits": [j]})
+        for k in reversed(range(j)):
+            lam = math.pi / (1 << (j - k))
+            phase(k, lam / 2)
+            ops.append({"kind": "cx", "qubits": [k, j]})
+            phase(j, -lam / 2)
+            ops.append({"kind": "cx", "qubits": [k, j]})
+            phase(j, lam / 2)
+    for i in range(n_qubits // 2):
+        a, b = i, n_qubits - 1 - i
+        ops += [{"kind": "cx", "qubits": [a, b]}, {"kind": "cx", "qubits": [b, a]},
+                {"kind": "cx", "qubits": [a, b]}]
+    if measure_all:
+        ops.append({"kind": "measure", "qubits": list(range(n_qubits)),
+                    "clbits": list(range(n_qubits))})
+    return {"n_qubits": n_qubits, "ops": ops}
+
+
+def qft_noise(p: float = 0.01, form: str = "pauli") -> Dict:
+    """1% depolarizing noise after every one-qubit (H, phase) and two-qubit
+    (CX) gate, as a Pauli channel or as the equivalent Kraus list."""
+    make = depolarizing_pauli if form == "pauli" else depolarizing_kraus
+    return noise_model([rule(["u3", "h", "x"], make(p, 1)), rule(["cx"], make(p, 2))])
+
+
 def kraus_channel(mats: Sequence) -> Dict:
     mats = [np.asarray(m, dtype=complex).tolist() for m in mats]
     nq = int(round(math.log2(len(mats[0]))))
