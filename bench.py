@@ -84,6 +84,31 @@ def other_form(circ, noise, seed, gates, shots, dtype, mode):
             if st["exec_ms"] > 0 else None}
 
 
+def qft_comparison(n, shots=4000, p=0.01, plain_shots=40):
+    """The paper's single-GPU experiment (Sec. V-A): QFT with 1% Pauli or
+    Kraus noise, 4000 shots, the batched and branched forms against the
+    plain per-shot form (timed on its first shot ids; linear in shots)."""
+    import workloads as W
+    circ = W.qft(n)
+    gates = W.count_gates(circ)
+    for form in ("pauli", "kraus"):
+        noise = W.qft_noise(p, form)
+        res = {}
+        for dtype, mode in (("c64", "batch"), ("c128", "batch"), ("c64", "branch"),
+                            ("c128", "branch")):
+            other_form(circ, noise, 0, gates, min(shots, 256), dtype, mode)  # warm-up
+            res[f"{dtype}_{mode}"] = other_form(circ, noise, 0, gates, shots, dtype, mode)
+        pl = other_form(circ, noise, 0, gates, plain_shots, "c128", "plain")
+        per_shot_ms = pl["ms"] / plain_shots
+        line = {"workload": f"qft_{n}q", "noise": f"{form} 1%", "shots": shots,
+                "gates_per_shot": gates,
+                "plain_fp64_ms_for_all_shots": round(per_shot_ms * shots, 1)}
+        for k, r in res.items():
+            line[k + "_ms"] = r["ms"]
+            line[k + "_speedup_over_plain"] = round(per_shot_ms * shots / r["ms"], 1)
+        print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +122,9 @@ def main():
                     help="skip the complex128 wave reported beside the c64 value")
     ap.add_argument("--plain-shots", type=int, default=16,
                     help="shots of the plain per-shot FP64 form timed for the speedup (0: skip)")
+    ap.add_argument("--qft", type=str, default="",
+                    help="instead of the headline workload: the paper's QFT comparison, "
+                         "comma-separated qubit counts (4000 shots, 1%% noise)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: shots shard across GPUs by "
@@ -107,6 +135,11 @@ def main():
     import torch
     import workloads as W
     from paper_2308_03399_amd import Simulator
+
+    if args.qft:
+        for n in [int(x) for x in args.qft.split(",")]:
+            qft_comparison(n)
+        return
 
     w = W.workload("c3_20q")
     circ, noise, seed = w["circuit"], w["noise"], w["seed"]

@@ -6,6 +6,7 @@
 // per-block partials in a fixed order, the same Philox draws as the other
 // modes), so the per-shot results equal those of batch and branch mode.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <stdint.h>
 
 #include "program.h"
@@ -299,15 +300,25 @@ __global__ void k_reduce(const typename V2<R>::T *st, int n, const DevOp *op, co
 __global__ void k_decide(const double *partial, int nblocks, int cnt, uint64_t seed, uint64_t shot,
                          const DevOp *op, Cell *cell, uint64_t *mem, double ro01, double ro10)
 {
+    // sum the per-block partials: each thread a strided share, then a
+    // fixed-order tree over the threads (the same order on every call)
+    __shared__ double part[kRed][kB];
     __shared__ double red[kRed];
-    const int v = threadIdx.x;
-    if (v < kRed) {
+    const int t = threadIdx.x;
+    for (int v = 0; v < kRed; ++v) {
         double s = 0;
-        for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * kRed + v];
-        red[v] = s;
+        for (int b = t; b < nblocks; b += kB) s += partial[(size_t)b * kRed + v];
+        part[v][t] = s;
     }
     __syncthreads();
-    if (v != 0) return;
+    for (int w = kB / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int v = 0; v < kRed; ++v) part[v][t] += part[v][t + w];
+        __syncthreads();
+    }
+    if (t < kRed) red[t] = part[t][0];
+    __syncthreads();
+    if (t != 0) return;
     const double u = philox_u01(seed, shot, op->r, 0);
     const double x = u * red[0];
     double run = 0;
@@ -448,6 +459,8 @@ static hipError_t plain_run_t(const DevOp *ops, const DevOp *hops, int n_ops, co
     const unsigned g1 = (unsigned)((namps + kB - 1) / kB);
     const unsigned g2 = (unsigned)((namps / 2 + kB - 1) / kB);
     const unsigned g4 = (unsigned)((namps / 4 + kB - 1) / kB);
+    // reduction grid sized to the state (one block per 1024 amplitudes)
+    red_blocks = (int)std::min<uint64_t>((uint64_t)red_blocks, std::max<uint64_t>(1, g4));
     for (uint64_t s = 0; s < n_shots; ++s) {
         const uint64_t shot = shot_base + s;
         uint64_t *mem = memory + s;
@@ -482,7 +495,7 @@ static hipError_t plain_run_t(const DevOp *ops, const DevOp *hops, int n_ops, co
                 const DevRule &hr = hrules[h.rule];
                 hipLaunchKernelGGL(k_reduce<R>, dim3(red_blocks), dim3(kB), 0, st, (const A *)S, n, d,
                                    rules, pool, partial);
-                hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, (const double *)partial,
+                hipLaunchKernelGGL(k_decide, dim3(1), dim3(kB), 0, st, (const double *)partial,
                                    red_blocks, (int)hr.n_terms, seed, shot, d, cell, mem, ro01, ro10);
                 const uint32_t dim = 1u << hr.nq;
                 if (hr.nq == 1)
@@ -504,7 +517,7 @@ static hipError_t plain_run_t(const DevOp *ops, const DevOp *hops, int n_ops, co
                 }
                 hipLaunchKernelGGL(k_reduce<R>, dim3(red_blocks), dim3(kB), 0, st, (const A *)S, n, d,
                                    rules, pool, partial);
-                hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, (const double *)partial,
+                hipLaunchKernelGGL(k_decide, dim3(1), dim3(kB), 0, st, (const double *)partial,
                                    red_blocks, 1 << h.nq, seed, shot, d, cell, mem, ro01, ro10);
                 hipLaunchKernelGGL(k_collapse<R>, dim3(g1), dim3(kB), 0, st, S, namps, d,
                                    (const Cell *)cell);
