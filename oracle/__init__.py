@@ -27,7 +27,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 KIND = {"id": 0, "x": 1, "y": 2, "z": 3, "h": 4, "s": 5, "sdg": 6, "t": 7,
         "tdg": 8, "u3": 9, "cx": 16, "cz": 17, "swap": 18, "unitary": 24,
-        "measure": 32, "reset": 33, "measure_reset": 34}
+        "measure": 32, "reset": 33, "measure_reset": 34, "bfunc": 40}
 PAULI_CODE = {"I": 0, "X": 1, "Y": 2, "Z": 3}
 MAXQ = 32
 
@@ -55,7 +55,7 @@ def lib():
         P = ctypes.c_void_p
         L.oracle_run.restype = ctypes.c_int
         L.oracle_run.argtypes = [
-            ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P, P, ctypes.c_int,
             P, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
             ctypes.c_uint64, ctypes.c_long, P, P, ctypes.c_int, P,
             ctypes.c_int]
@@ -89,11 +89,17 @@ def _pack(circuit: Dict, noise: Optional[Dict]):
     c = np.full(n_ops * MAXQ, -1, dtype=np.int32)
     par = np.zeros(n_ops * 3, dtype=np.float64)
     mat_off = np.full(n_ops, -1, dtype=np.int64)
+    cmask = np.zeros(n_ops, dtype=np.uint64)
+    cval = np.zeros(n_ops, dtype=np.uint64)
     mats = []
     moff = 0
     for i, op in enumerate(ops):
         kind[i] = KIND[op["kind"]]
-        qs = list(op["qubits"])
+        qs = list(op.get("qubits", []))
+        if op["kind"] == "bfunc":           # predicate of the branch op
+            cmask[i], cval[i] = int(op["mask"]), int(op["value"])
+        elif op.get("cond"):                # condition of a conditional op
+            cmask[i], cval[i] = int(op["cond"][0]), int(op["cond"][1])
         nq[i] = len(qs)
         q[i * MAXQ:i * MAXQ + len(qs)] = qs
         cl = list(op.get("clbits", []))
@@ -149,7 +155,7 @@ def _pack(circuit: Dict, noise: Optional[Dict]):
     codes = np.asarray(codes if codes else [0], dtype=np.int32)
     kmats = np.concatenate(kmats) if kmats else np.zeros(1)
     ro = (noise or {}).get("readout", [0.0, 0.0])
-    return dict(kind=kind, nq=nq, q=q, c=c, par=par, mat_off=mat_off,
+    return dict(kind=kind, nq=nq, q=q, c=c, par=par, cmask=cmask, cval=cval, mat_off=mat_off,
                 mats=mats, n_rules=n_rules, gmask=gmask, rtype=rtype,
                 rnq=rnq, rnt=rnt, roff=roff, probs=probs, codes=codes,
                 kmats=kmats, ro01=float(ro[0]), ro10=float(ro[1]))
@@ -179,7 +185,7 @@ def run(circuit: Dict, noise: Optional[Dict], shots, seed: int = 0,
     n_x = lib().oracle_run(
         n, len(circuit["ops"]), a["kind"].ctypes.data, a["nq"].ctypes.data,
         a["q"].ctypes.data, a["c"].ctypes.data, a["par"].ctypes.data,
-        a["mat_off"].ctypes.data, a["mats"].ctypes.data, a["n_rules"],
+        a["cmask"].ctypes.data, a["cval"].ctypes.data, a["mat_off"].ctypes.data, a["mats"].ctypes.data, a["n_rules"],
         a["gmask"].ctypes.data, a["rtype"].ctypes.data, a["rnq"].ctypes.data,
         a["rnt"].ctypes.data, a["roff"].ctypes.data, a["probs"].ctypes.data,
         a["codes"].ctypes.data, a["kmats"].ctypes.data, a["ro01"], a["ro10"],

@@ -94,17 +94,32 @@ def _pauli_matrix(s: str) -> np.ndarray:
 
 
 def expand(circuit: Dict, noise: Dict) -> List[Dict]:
+    """Noise sites after every matching gate; a conditional gate's channels
+    carry its condition."""
     rules = (noise or {}).get("rules", [])
     out = []
     for op in circuit["ops"]:
         out.append(op)
-        if op["kind"] in _NON_GATES:
+        if op["kind"] in _NON_GATES or op["kind"] == "bfunc":
             continue
         for ru in rules:
             if op["kind"] in ru["gates"] and ru["nq"] == len(op["qubits"]):
-                out.append({"kind": "channel", "rule": ru,
+                out.append({"kind": "channel", "rule": ru, "cond": op.get("cond"),
                             "qubits": list(op["qubits"])})
     return out
+
+
+def _holds(op: Dict, creg: int) -> bool:
+    """Condition of an op (Sec. IV-A conditional gates): (creg & mask) == value."""
+    cond = op.get("cond")
+    return not cond or (creg & int(cond[0])) == int(cond[1])
+
+
+def _bfunc(op: Dict, creg: int) -> int:
+    """Branch op: its clbit becomes ((creg & mask) == value)."""
+    bit = 1 if (creg & int(op["mask"])) == int(op["value"]) else 0
+    cb = op["clbits"][0]
+    return (creg & ~(1 << cb)) | (bit << cb)
 
 
 def _channel_ops(ru: Dict) -> List[Tuple[float, np.ndarray]]:
@@ -155,6 +170,15 @@ def creg_distribution_dm(circuit: Dict, noise: Dict) -> Dict[int, float]:
     for op in expand(circuit, noise):
         new: Dict[int, np.ndarray] = {}
         k = op["kind"]
+        if k == "bfunc":
+            for cr, rho in states.items():
+                key = _bfunc(op, cr)
+                new[key] = new.get(key, 0) + rho
+            states = new
+            continue
+        # registers whose condition fails keep their state untouched
+        skipped = {cr: rho for cr, rho in states.items() if not _holds(op, cr)}
+        states = {cr: rho for cr, rho in states.items() if _holds(op, cr)}
         if k == "channel":
             mats = [(p, embed(m, op["qubits"], n)) for p, m in
                     _channel_ops(op["rule"])]
@@ -189,6 +213,8 @@ def creg_distribution_dm(circuit: Dict, noise: Dict) -> Dict[int, float]:
             U = embed(gate_matrix(op), op["qubits"], n)
             for cr, rho in states.items():
                 new[cr] = U @ rho @ U.conj().T
+        for cr, rho in skipped.items():
+            new[cr] = new.get(cr, 0) + rho
         states = new
     return {cr: float(np.real(np.trace(rho))) for cr, rho in states.items()}
 
@@ -200,6 +226,8 @@ def creg_distribution_tree(circuit: Dict, noise: Dict,
     xops = expand(circuit, noise)
     full = {}
     for i, op in enumerate(xops):
+        if op["kind"] == "bfunc":
+            continue
         if op["kind"] == "channel":
             full[i] = [(p, embed(m, op["qubits"], n)) for p, m in
                        _channel_ops(op["rule"])]
@@ -219,6 +247,12 @@ def creg_distribution_tree(circuit: Dict, noise: Dict,
             return
         op = xops[i]
         k = op["kind"]
+        if k == "bfunc":
+            walk(i + 1, psi, w, _bfunc(op, creg))
+            return
+        if not _holds(op, creg):
+            walk(i + 1, psi, w, creg)
+            return
         if k == "channel":
             for p, E in full[i]:
                 phi = E @ psi

@@ -28,6 +28,12 @@
  *    outcome i runs over 0..2^|Q|-1 with bit t of i the value of qubit
  *    Q[t]; the state collapses onto the chosen outcome and is renormalised;
  *    reset (alone or after a measure) then returns measured 1s to |0>.
+ *  - Conditional operations (Sec. IV-A: conditional gates refer to measured
+ *    classical bits, branch operations set a classical bit from them): an
+ *    op with a non-zero condition mask runs only if (creg & mask) == value,
+ *    and the noise channels attached to a conditional gate carry the same
+ *    condition; a branch op sets its clbit to ((creg & mask) == value). A
+ *    skipped op keeps its place in the op numbering (its draws are unused).
  *  - Readout error (named in Sec. III-B, no model given): each recorded bit
  *    flips independently, 0->1 with p01 and 1->0 with p10, from its own draw.
  *  - Random numbers: u = U(seed, shot, r, d) from Philox4x32-10 (Salmon,
@@ -52,6 +58,7 @@ enum {
     O_CX = 16, O_CZ, O_SWAP,
     O_UNITARY = 24,
     O_MEASURE = 32, O_RESET, O_MEASURE_RESET,
+    O_BFUNC = 40,      /* clbit c[0] <- ((creg & cmask) == cval) */
     /* inserted by the noise expansion only */
     O_PAULI_CH = 48, O_KRAUS_CH
 };
@@ -67,6 +74,8 @@ typedef struct {
     double par[3];
     const double *mat; /* UNITARY / KRAUS matrices, interleaved re/im */
     int rule;          /* noise rule index for channel ops */
+    uint64_t cmask;    /* condition (or branch-op predicate): (creg & cmask) == cval */
+    uint64_t cval;
 } xop;
 
 typedef struct {
@@ -340,7 +349,7 @@ static void reset_measured(cplx *psi, int n, const xop *op, uint64_t outcome)
 /* ------------------------------------------------------------------------ */
 static int is_gate(int kind)
 {
-    return kind < O_MEASURE;
+    return kind < O_MEASURE;  /* channels copy the gate's condition too */
 }
 
 static int expand(int n_ops, const xop *ops, int n_rules, const xrule *rules,
@@ -381,6 +390,12 @@ static uint64_t run_shot(int n, int n_x, const xop *x, const xrule *rules,
     int end = (stop_at >= 0 && stop_at < n_x) ? stop_at : n_x;
     for (int r = 0; r < end; ++r) {
         const xop *op = &x[r];
+        if (op->kind == O_BFUNC) {
+            const uint64_t bit = (creg & op->cmask) == op->cval;
+            creg = (creg & ~(1ull << op->c[0])) | (bit << op->c[0]);
+            continue;
+        }
+        if (op->cmask && (creg & op->cmask) != op->cval) continue;
         switch (op->kind) {
         case O_CX: apply_cx(psi, n, op->q[0], op->q[1]); break;
         case O_CZ: apply_cz(psi, n, op->q[0], op->q[1]); break;
@@ -435,6 +450,7 @@ static uint64_t run_shot(int n, int n_x, const xop *x, const xrule *rules,
 /* ------------------------------------------------------------------------ */
 int oracle_run(int n, int n_ops, const int *kind, const int *nq,
                const int *q, const int *c, const double *par,
+               const uint64_t *cmask, const uint64_t *cval,
                const long *mat_off, const double *mats, int n_rules,
                const unsigned *gate_mask, const int *rtype, const int *rnq,
                const int *rnterms, const long *roff, const double *probs,
@@ -461,6 +477,12 @@ int oracle_run(int n, int n_ops, const int *kind, const int *nq,
         for (int t = 0; t < 3; ++t) ops[i].par[t] = par[i * 3 + t];
         ops[i].mat = mat_off[i] >= 0 ? mats + mat_off[i] : NULL;
         ops[i].rule = -1;
+        ops[i].cmask = cmask[i];
+        ops[i].cval = cval[i];
+        if ((cval[i] & ~cmask[i]) != 0) { free(ops); free(rules); return -1; }
+        if (kind[i] == O_BFUNC && (nq[i] != 0 || c[i * MAXQ] < 0 || c[i * MAXQ] > 63)) {
+            free(ops); free(rules); return -1;
+        }
     }
     for (int r = 0; r < n_rules; ++r) {
         if (rnq[r] < 1 || rnq[r] > MAXDENSE) { free(ops); free(rules); return -1; }

@@ -368,3 +368,60 @@ def test_depolarizing_kraus_form_equals_pauli_form():
     _sample_check(mem, d1, 40000)
     mem2 = oracle.run(circ, W.noise_model(rules_k), 20000, seed=4)
     _sample_check(mem2, dk, 20000)
+
+
+def test_feed_forward_conditional_closed_form():
+    # H, measure q0 -> c0, X on q1 only if c0 == 1, measure q1 -> c1:
+    # the register is 00 or 11, each with probability 1/2 exactly, and with
+    # readout error the conditional follows the recorded (flipped) bit
+    ops = [{"kind": "h", "qubits": [0]},
+           {"kind": "measure", "qubits": [0], "clbits": [0]},
+           {"kind": "x", "qubits": [1], "cond": [1, 1]},
+           {"kind": "measure", "qubits": [1], "clbits": [1]}]
+    circ = {"n_qubits": 2, "n_clbits": 2, "ops": ops}
+    d = dm.creg_distribution_dm(circ, None)
+    assert abs(d[0] - 0.5) < 1e-14 and abs(d[3] - 0.5) < 1e-14
+    assert all(v < 1e-15 for k, v in d.items() if k not in (0, 3))
+    ro = (0.1, 0.2)
+    dr = dm.creg_distribution_dm(circ, W.noise_model([], readout=ro))
+    # c0 recorded 1 with prob (1/2)(p01) + (1/2)(1-p10); then q1 = 1 and c1 reads it
+    pc0 = 0.5 * ro[0] + 0.5 * (1 - ro[1])
+    assert abs(dr.get(3, 0) - pc0 * (1 - ro[1])) < 1e-14
+    assert abs(dr.get(1, 0) - pc0 * ro[1]) < 1e-14
+    assert abs(dr.get(2, 0) - (1 - pc0) * ro[0]) < 1e-14
+    mem = oracle.run(circ, None, 20000, seed=2)
+    assert set(np.unique(mem).tolist()) <= {0, 3}
+    _sample_check(mem, d, 20000)
+
+
+def test_branch_op_sets_bit_from_register():
+    # Bell pair measured into c0 c1; the branch op writes c2 = (c0c1 == 11)
+    ops = [{"kind": "h", "qubits": [0]}, {"kind": "cx", "qubits": [0, 1]},
+           {"kind": "measure", "qubits": [0, 1], "clbits": [0, 1]},
+           {"kind": "bfunc", "clbits": [2], "mask": 3, "value": 3},
+           {"kind": "x", "qubits": [0], "cond": [4, 4]},
+           {"kind": "measure", "qubits": [0], "clbits": [3]}]
+    circ = {"n_qubits": 2, "n_clbits": 4, "ops": ops}
+    d = dm.creg_distribution_dm(circ, None)
+    # 00 -> c2=0, q0 stays 0; 11 -> c2=1, X flips q0 back to 0
+    assert abs(d[0b0000] - 0.5) < 1e-14 and abs(d[0b0111] - 0.5) < 1e-14
+    t = dm.creg_distribution_tree(circ, None)
+    assert dm.tvd(d, t) < 1e-14
+    mem = oracle.run(circ, None, 4000, seed=5)
+    assert set(np.unique(mem).tolist()) <= {0b0000, 0b0111}
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_conditionals_dm_equals_tree_and_oracle_samples(seed):
+    n = 2
+    circ = W.random_small(n, 5, seed=40 + seed, kinds=["u3", "h", "t", "s", "cx", "cz"],
+                          n_mid=2, p_cond=0.7)
+    assert any(op.get("cond") for op in circ["ops"])
+    noise = _random_noise(seed)
+    d = dm.creg_distribution_dm(circ, noise)
+    t = dm.creg_distribution_tree(circ, noise)
+    assert abs(sum(d.values()) - 1) < 1e-12
+    assert dm.tvd(d, t) < 1e-12
+    shots = 30000
+    mem = oracle.run(circ, noise, shots, seed=17 + seed)
+    _sample_check(mem, d, shots)

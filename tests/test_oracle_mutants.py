@@ -47,6 +47,12 @@ MUTANTS = [
     ("measure_bit_order_reversed", "for (int t = 0; t < m; ++t) pat |= ((i >> op->q[t]) & 1ull) << t;\n        P[pat]",
      "for (int t = 0; t < m; ++t) pat |= ((i >> op->q[m - 1 - t]) & 1ull) << t;\n        P[pat]",
      [T.test_dm_equals_tree_and_oracle_samples]),
+    ("condition_ignored", "if (op->cmask && (creg & op->cmask) != op->cval) continue;",
+     "if (0 && op->cmask && (creg & op->cmask) != op->cval) continue;",
+     [T.test_feed_forward_conditional_closed_form, T.test_conditionals_dm_equals_tree_and_oracle_samples]),
+    ("branch_op_inverted", "const uint64_t bit = (creg & op->cmask) == op->cval;",
+     "const uint64_t bit = (creg & op->cmask) != op->cval;",
+     [T.test_branch_op_sets_bit_from_register]),
 ]
 
 

@@ -279,9 +279,23 @@ def serving_stream(n_requests: int, rate_per_s: float, seed: int = 0,
 # ----------------------------------------------------------------------------
 
 def random_small(n_qubits: int, n_ops: int, seed: int, kinds=None,
-                 measure_all: bool = True, n_mid: int = 0) -> Dict:
-    """Random mixed circuit over the supported op kinds, for parity tests."""
+                 measure_all: bool = True, n_mid: int = 0, p_cond: float = 0.0) -> Dict:
+    """Random mixed circuit over the supported op kinds, for parity tests.
+    With p_cond > 0, gates after a mid-circuit measure are made conditional
+    on already written clbits with that probability, and each mid-circuit
+    measure is followed by a branch op (bfunc) on a fresh clbit."""
     rng = np.random.default_rng(seed)
+    crng = np.random.default_rng(seed + 7919)
+    written: List[int] = []
+
+    def maybe_cond(op):
+        if p_cond > 0 and written and crng.random() < p_cond:
+            bits = [int(b) for b in crng.choice(written, min(len(written), int(crng.integers(1, 3))),
+                                                 replace=False)]
+            mask = sum(1 << b for b in bits)
+            value = sum((int(crng.integers(2)) << b) for b in bits)
+            op["cond"] = [mask, value]
+        return op
     kinds = kinds or ["u3", "h", "x", "y", "z", "s", "t", "sdg", "tdg",
                       "cx", "cz", "swap", "unitary2"]
     if n_qubits < 2:
@@ -296,24 +310,32 @@ def random_small(n_qubits: int, n_ops: int, seed: int, kinds=None,
             op = {"kind": k, "qubits": [q]}
             if k == "u3":
                 op["params"] = [float(x) for x in rng.uniform(0, 2 * math.pi, 3)]
-            ops.append(op)
+            ops.append(maybe_cond(op))
         elif k == "unitary2":
             a, b = (int(x) for x in rng.choice(n_qubits, 2, replace=False))
             z = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
             qm, rm = np.linalg.qr(z)
             qm = qm * (np.diag(rm) / np.abs(np.diag(rm)))
-            ops.append({"kind": "unitary", "qubits": [a, b],
-                        "matrix": [[complex(v) for v in row] for row in qm]})
+            ops.append(maybe_cond({"kind": "unitary", "qubits": [a, b],
+                                   "matrix": [[complex(v) for v in row] for row in qm]}))
         else:
             a, b = (int(x) for x in rng.choice(n_qubits, 2, replace=False))
-            ops.append({"kind": k, "qubits": [a, b]})
+            ops.append(maybe_cond({"kind": k, "qubits": [a, b]}))
         if i in mid_at:
             m = int(rng.integers(1, min(3, n_qubits) + 1))
             qs = [int(x) for x in rng.choice(n_qubits, m, replace=False)]
             cl = list(range(n_cl, n_cl + m))
             n_cl += m
             kind = "measure_reset" if rng.integers(2) else "measure"
-            ops.append({"kind": kind, "qubits": qs, "clbits": cl})
+            ops.append(maybe_cond({"kind": kind, "qubits": qs, "clbits": cl}))
+            if p_cond > 0:
+                written += cl
+                bits = [int(b) for b in crng.choice(written, min(len(written), 2), replace=False)]
+                ops.append({"kind": "bfunc", "clbits": [n_cl],
+                            "mask": sum(1 << b for b in bits),
+                            "value": sum((int(crng.integers(2)) << b) for b in bits)})
+                written.append(n_cl)
+                n_cl += 1
     if measure_all:
         ops.append({"kind": "measure", "qubits": list(range(n_qubits)),
                     "clbits": list(range(n_qubits))})
