@@ -71,7 +71,9 @@ typedef enum {
     SV_OP_UNITARY = 30,   /* 1 or 2 qubits, dense matrix in mat            */
     SV_OP_MEASURE = 40,   /* qubits -> clbits (Sec. IV-A measure)           */
     SV_OP_RESET,          /* measure without record, then back to |0>      */
-    SV_OP_MEASURE_RESET   /* measure -> clbits, then back to |0>           */
+    SV_OP_MEASURE_RESET,  /* measure -> clbits, then back to |0>           */
+    SV_OP_BFUNC = 45      /* branch op (Sec. IV-A): no qubits; clbit c[0] is
+                             set to ((creg & cond_mask) == cond_value)     */
 } sv_op_kind;
 
 #define SV_MAX_INLINE 8   /* qubits/clbits held inline in sv_op            */
@@ -87,6 +89,12 @@ typedef struct {
                                        interleaved re/im; copied during the call   */
     const uint32_t *q_ext;          /* qubits when nq > SV_MAX_INLINE, else NULL   */
     const uint32_t *c_ext;          /* clbits when nq > SV_MAX_INLINE, else NULL   */
+    uint64_t cond_mask;             /* conditional op (Sec. IV-A): it runs, with the
+                                       noise attached to it, only for shots whose
+                                       register satisfies (creg & cond_mask) ==
+                                       cond_value; 0 = unconditional. For
+                                       SV_OP_BFUNC: the predicate it records.   */
+    uint64_t cond_value;            /* bits outside cond_mask must be 0 (EINVAL) */
 } sv_op;
 
 /* Pauli channel (Sec. III-B, Table I): n_terms (probability, Pauli string)

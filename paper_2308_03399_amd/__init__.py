@@ -25,7 +25,7 @@ STATUS = {0: "SV_OK", 1: "SV_EINVAL", 2: "SV_ENOMEM", 3: "SV_EDEVICE",
           4: "SV_ESTATE", 5: "SV_EUNSUPPORTED"}
 OP_KIND = {"id": 1, "x": 2, "y": 3, "z": 4, "h": 5, "s": 6, "sdg": 7, "t": 8,
            "tdg": 9, "u3": 10, "cx": 20, "cz": 21, "swap": 22, "unitary": 30,
-           "measure": 40, "reset": 41, "measure_reset": 42}
+           "measure": 40, "reset": 41, "measure_reset": 42, "bfunc": 45}
 PAULI_CODE = {"I": 0, "X": 1, "Y": 2, "Z": 3}
 MAX_INLINE = 8
 
@@ -48,7 +48,8 @@ class sv_op(ctypes.Structure):
                 ("p", ctypes.c_double * 3),
                 ("mat", ctypes.POINTER(ctypes.c_double)),
                 ("q_ext", ctypes.POINTER(ctypes.c_uint32)),
-                ("c_ext", ctypes.POINTER(ctypes.c_uint32))]
+                ("c_ext", ctypes.POINTER(ctypes.c_uint32)),
+                ("cond_mask", ctypes.c_uint64), ("cond_value", ctypes.c_uint64)]
 
 
 class sv_pauli_channel(ctypes.Structure):
@@ -216,7 +217,7 @@ def marshal(circuit: Dict, noise: Optional[Dict]) -> Dict:
     for i, op in enumerate(ops):
         o = arr[i]
         o.kind = OP_KIND[op["kind"]]
-        qs = [int(q) for q in op["qubits"]]
+        qs = [int(q) for q in op.get("qubits", [])]
         cs = [int(c) for c in op.get("clbits", [])]
         o.nq = len(qs)
         if len(qs) <= MAX_INLINE:
@@ -232,6 +233,10 @@ def marshal(circuit: Dict, noise: Optional[Dict]) -> Dict:
             o.c_ext = ctypes.cast(ca, ctypes.POINTER(ctypes.c_uint32))
         for t, p in enumerate(op.get("params", [])):
             o.p[t] = float(p)
+        if op["kind"] == "bfunc":
+            o.cond_mask, o.cond_value = int(op["mask"]), int(op["value"])
+        elif op.get("cond"):
+            o.cond_mask, o.cond_value = int(op["cond"][0]), int(op["cond"][1])
         if op["kind"] == "unitary":
             m = np.asarray(op["matrix"], dtype=np.complex128)
             flat = np.ascontiguousarray(np.stack([m.real, m.imag], -1).ravel())

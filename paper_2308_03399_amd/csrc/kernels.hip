@@ -214,6 +214,7 @@ struct WgShared {
     double wred[kMaxRed][kWG / 64];
     double tsum_n;
     int term_tile;
+    int split_cond;  // STOP_SPLIT: the stopping op's condition differs between shots
     int n_ug;
     uint64_t pass_flops;
     unsigned long long st[ST_COUNT];
@@ -500,6 +501,7 @@ template <class R>
 __device__ __noinline__ void apply_op(Ctx<R> &c, const DevOp &op, int d, double s)
 {
     const ExecParams &P = c.P;
+    if (op.kind == DK_BFUNC || ((op.flags & DF_COND) && d == kSkip)) return;
     switch (op.kind) {
     case DK_MAT1: {
         const Mat2<R> m = load_m2<R>(P.pool + op.mat, 1.0);
@@ -976,6 +978,7 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
             const DevOp &op = P.ops[o];
             const int d = c.dec[o - S.start];
             const double sc = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
+            if (op.kind == DK_BFUNC || ((op.flags & DF_COND) && d == kSkip)) continue;
             switch (op.kind) {
             case DK_MAT1:
                 fuse_factor(c, op.rb[0], P.pool + op.mat, 1.0, pend_set);
@@ -1339,16 +1342,28 @@ __device__ __forceinline__ int red_count(const ExecParams &P, const DevOp &op)
 }
 
 // Record measured bits (with readout flips) of shot `shot`.
+// A shot's classical register is read back on the device (conditions,
+// branch ops) after other waves wrote it: device-scope accesses, which do
+// not stop at a compute unit's own cache.
+__device__ __forceinline__ uint64_t creg_load(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void creg_store(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __noinline__ void record_bits(const ExecParams &P, const DevOp &op, uint64_t shot, uint32_t o)
 {
-    uint64_t m = P.memory[shot];
+    uint64_t m = creg_load(P.memory + shot);
     for (int t = 0; t < op.nq; ++t) {
         uint64_t bit = (o >> t) & 1u;
         const double pf = bit ? P.ro10 : P.ro01;
         if (pf > 0 && philox_u01(P.seed, P.shot_base + shot, op.r, 1u + t) < pf) bit ^= 1u;
         m = (m & ~(1ull << op.c[t])) | (bit << op.c[t]);
     }
-    P.memory[shot] = m;
+    creg_store(P.memory + shot, m);
 }
 
 // Outcome of shot `shot` at random op `op` (after its reduction, if any).
@@ -1358,6 +1373,40 @@ __device__ __forceinline__ int outcome_of(const ExecParams &P, const lds<WgShare
     const double u = philox_u01(P.seed, P.shot_base + shot, op.r, 0);
     if (op.kind == DK_PAULI) return pauli_pick(P, P.rules[op.rule], u);
     return red_pick(S, red_count(P, op), u);
+}
+
+// Value of a condition (or branch-op predicate) for one shot.
+__device__ __forceinline__ int cond_of(const ExecParams &P, const DevOp &op, uint64_t shot)
+{
+    return (creg_load(P.memory + shot) & op.cond_mask) == op.cond_value ? 1 : 0;
+}
+
+// Classical-register op of the record's shots (Sec. IV-A): a branch op
+// writes each shot's clbit; a condition is evaluated for every shot.
+// Returns 0 (false for every shot), 1 (true for every shot) or 2 (mixed).
+template <class R>
+__device__ __noinline__ int creg_op(Ctx<R> &c, const DevOp &op)
+{
+    const ExecParams &P = c.P;
+    lds<WgShared> &S = c.S;
+    if (c.tid == 0) { S.omin = 1; S.omax = 0; }
+    __syncthreads();
+    int lmin = 1, lmax = 0;
+    for (int i = S.lo + c.tid; i < S.hi; i += kWG) {
+        const uint64_t shot = (uint64_t)P.shot_perm[i];
+        const uint64_t creg = creg_load(P.memory + shot);
+        const int t = (creg & op.cond_mask) == op.cond_value ? 1 : 0;
+        if (op.kind == DK_BFUNC)
+            creg_store(P.memory + shot, (creg & ~(1ull << op.c[0])) | ((uint64_t)t << op.c[0]));
+        lmin = min(lmin, t);
+        lmax = max(lmax, t);
+    }
+    if (lmin == 0) atomicMin((int *)&S.omin, 0);
+    if (lmax == 1) atomicMax((int *)&S.omax, 1);
+    __syncthreads();  // also orders the branch op's stores before later reads
+    const int r = S.omin == S.omax ? S.omin : 2;
+    __syncthreads();
+    return r;
 }
 
 // ----------------------------------------------------------- the kernel
@@ -1383,11 +1432,14 @@ __device__ __noinline__ void copy_state_to_slot(Ctx<R> &c, int dst, int src_slot
 // Partition the branch's shots by outcome at op j and continue with the
 // first group; other groups get a copied state (or the waiting list).
 template <class R>
-__device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
+__device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j, bool cnd)
 {
     const ExecParams &P = c.P;
     lds<WgShared> &S = c.S;
     const int tid = c.tid;
+    // cnd: the op's condition differs between the record's shots, which are
+    // split by its value; each part then finds it uniform and runs or skips
+    // the op. Otherwise the split is by the op's drawn outcome.
     const int m = S.hi - S.lo;
     const int chunk = (m + kWG - 1) / kWG;
     const int my_lo = S.lo + min(m, tid * chunk), my_hi = S.lo + min(m, (tid + 1) * chunk);
@@ -1395,7 +1447,8 @@ __device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
 #pragma unroll
     for (int o = 0; o < 16; ++o) my_cnt[o] = 0;
     for (int i = my_lo; i < my_hi; ++i) {
-        const int o = outcome_of(P, S, op, (uint64_t)P.shot_perm[i]);
+        const uint64_t sh = (uint64_t)P.shot_perm[i];
+        const int o = cnd ? cond_of(P, op, sh) : outcome_of(P, S, op, sh);
 #pragma unroll
         for (int q = 0; q < 16; ++q) my_cnt[q] += (o == q);
     }
@@ -1423,8 +1476,22 @@ __device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
             ++g;
         }
         S.n_groups = g;
+        // a condition split must divide the record, else it would recur
+        // forever at the same op: end the record with an error instead
+        if (cnd && g < 2) {
+            atomicOr(&P.ctl->error, kErrState);
+            S.n_groups = 0;
+        }
     }
     __syncthreads();
+    if (S.n_groups == 0) {
+        if (tid == 0) {
+            S.cursor = P.n_ops;
+            S.pending = -1;
+        }
+        __syncthreads();
+        return;
+    }
     // scatter into shot_tmp, then copy back
     {
         int pos[16];
@@ -1436,13 +1503,13 @@ __device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
         }
         for (int i = my_lo; i < my_hi; ++i) {
             const int shot = P.shot_perm[i];
-            const int o = outcome_of(P, S, op, (uint64_t)shot);
+            const int o = cnd ? cond_of(P, op, (uint64_t)shot) : outcome_of(P, S, op, (uint64_t)shot);
             int p = 0;
 #pragma unroll
             for (int q = 0; q < 16; ++q)
                 if (o == q) p = pos[q]++;
             P.shot_tmp[p] = shot;
-            if (op.kind == DK_MEASURE && (op.flags & DF_RECORD))
+            if (!cnd && op.kind == DK_MEASURE && (op.flags & DF_RECORD))
                 record_bits(P, op, (uint64_t)shot, (uint32_t)o);
         }
     }
@@ -1451,7 +1518,7 @@ __device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
     for (int i = S.lo + tid; i < S.hi; i += kWG) P.shot_perm[i] = P.shot_tmp[i];
     __syncthreads();
 
-    const bool measure_like = op.kind != DK_PAULI;
+    const bool measure_like = op.kind != DK_PAULI && !cnd;
     for (int g = 1; g < S.n_groups; ++g) {
         const int o = S.grp_o[g];
         const double sc = measure_like ? 1.0 / sqrt(S.red[1 + o]) : 1.0;
@@ -1468,7 +1535,7 @@ __device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
                 r.lo = S.grp_lo[g];
                 r.hi = S.grp_hi[g];
                 r.cursor = j;
-                r.pending = o;
+                r.pending = cnd ? -1 : o;
                 r.flags = child_fresh ? 1 : 0;
                 r.scale = sc;
                 r.norm_lb = measure_like ? 1.0 : S.norm_lb;
@@ -1491,7 +1558,7 @@ __device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j)
         S.lo = S.grp_lo[0];
         S.hi = S.grp_hi[0];
         S.cursor = j;
-        S.pending = o;
+        S.pending = cnd ? -1 : o;
         S.first_scale = measure_like ? 1.0 / sqrt(S.red[1 + o]) : 1.0;
         if (measure_like) S.norm_lb = 1.0;
         S.st[ST_SPLITS] += 1;
@@ -1526,11 +1593,31 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
     for (;;) {
         while (j < end_static && j - start < kMaxPassOps) {
             const uint16_t kd = P.ops[j].kind;
-            if (kd == DK_PAULI || kd == DK_KRAUS || kd == DK_MEASURE) break;
+            if (kd == DK_PAULI || kd == DK_KRAUS || kd == DK_MEASURE || kd == DK_BFUNC ||
+                (P.ops[j].flags & DF_COND))
+                break;
             ++j;
         }
         if (j >= end_static || j - start >= kMaxPassOps) break;
         const DevOp &op = P.ops[j];
+        if (op.kind == DK_BFUNC || (op.flags & DF_COND)) {
+            const int v = creg_op(c, op);
+            if (op.kind == DK_BFUNC || v == 0) {  // done / skipped for every shot
+                if (tid == 0) c.dec[j - start] = kSkip;
+                ++j;
+                continue;
+            }
+            if (v == 2) {
+                if (tid == 0) S.split_cond = 1;
+                stop = STOP_SPLIT;
+                break;
+            }
+            if (op.kind != DK_PAULI && op.kind != DK_KRAUS && op.kind != DK_MEASURE) {
+                if (tid == 0) c.dec[j - start] = 0;  // a gate whose condition holds for every shot
+                ++j;
+                continue;
+            }
+        }
         if (op.kind == DK_MEASURE) {
             stop = (op.flags & DF_TERMINAL) ? STOP_TERMINAL : STOP_REDUCE;
             break;
@@ -1584,6 +1671,7 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
                 ++j;
                 continue;
             }
+            if (tid == 0) S.split_cond = 0;
             stop = STOP_SPLIT;
             break;
         }
@@ -1806,7 +1894,7 @@ __device__ __noinline__ void decide(Ctx<R> &c)
         return;
     }
     if (P.branch_mode) {
-        split_branch(c, op, j);
+        split_branch(c, op, j, false);  // by outcome, whatever split came before
         return;
     }
     // several shots on one state without splitting cannot happen
@@ -1963,14 +2051,14 @@ __device__ __noinline__ void terminal_sample(Ctx<R> &c)
                 while (e > 0 && !(D[e] > D[e - 1])) --e;
             }
             const uint64_t idx = ((uint64_t)t << k) | e;
-            uint64_t mm = P.memory[shot];
+            uint64_t mm = creg_load(P.memory + shot);
             for (int q = 0; q < n; ++q) {
                 uint64_t bit = (idx >> q) & 1u;
                 const double pf = bit ? P.ro10 : P.ro01;
                 if (pf > 0 && philox_u01(P.seed, P.shot_base + shot, op.r, 1u + q) < pf) bit ^= 1u;
                 mm = (mm & ~(1ull << op.c[q])) | (bit << op.c[q]);
             }
-            P.memory[shot] = mm;
+            creg_store(P.memory + shot, mm);
         }
         __syncthreads();
     }
@@ -2183,7 +2271,7 @@ exec_kernel(ExecParams P)
                 continue;
             }
             // STOP_SPLIT on a Pauli channel
-            split_branch(c, P.ops[S.stop_op], S.stop_op);
+            split_branch(c, P.ops[S.stop_op], S.stop_op, S.split_cond != 0);
         }
 
         // ---- release the state and finish the record

@@ -28,13 +28,18 @@ enum DevKind : uint16_t {
     DK_PAULI = 6,    // Pauli channel of rule `rule`
     DK_KRAUS = 7,    // Kraus channel of rule `rule`
     DK_MEASURE = 8,  // measure / reset / measure+reset of q[0..nq-1]
+    DK_BFUNC = 9,    // clbit c[0] <- ((creg & cond_mask) == cond_value)
 };
+
+// decision of an op whose condition fails (it is skipped)
+constexpr int kSkip = -2;
 
 enum DevFlags : uint8_t {
     DF_DIAG = 1,      // DK_MAT1: off-diagonal entries are zero
     DF_RECORD = 2,    // DK_MEASURE: write clbits
     DF_RESET = 4,     // DK_MEASURE: return measured 1s to |0>
     DF_TERMINAL = 8,  // DK_MEASURE: last op, all qubits in order (sampling)
+    DF_COND = 16,     // runs only for shots with (creg & cond_mask) == cond_value
 };
 
 struct DevOp {
@@ -50,6 +55,8 @@ struct DevOp {
     uint8_t lb[8];       // tile-local bit of each qubit in its static pass
     uint8_t rb[8];       // register bit of each qubit in its group
     uint8_t c[32];       // clbits (terminal measure: clbit of qubit t)
+    uint64_t cond_mask;  // DF_COND / DK_BFUNC: predicate on the classical register
+    uint64_t cond_value;
 };
 
 // A register group: consecutive ops of a pass whose qubits lie on at most

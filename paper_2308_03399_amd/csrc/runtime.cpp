@@ -224,6 +224,7 @@ static void layout(sv_batch *b)
 struct XOp {  // expanded op
     int kind;       // sv_op_kind, or -1 Pauli channel, -2 Kraus channel
     int rule;
+    uint64_t cond_mask = 0, cond_value = 0;  // condition (BFUNC: its predicate)
     std::vector<int> q, c;
     double p[3];
     std::vector<cd> mat;  // gates: dense matrix (row-major, bit t <-> q[t])
@@ -345,6 +346,21 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
         const uint32_t k = op.kind;
         const bool gate = is_gate_kind(k);
         const bool meas = k == SV_OP_MEASURE || k == SV_OP_RESET || k == SV_OP_MEASURE_RESET;
+        if (op.cond_value & ~op.cond_mask)
+            return fail(SV_EINVAL, "op %zu: condition value has bits outside its mask", i);
+        if (k == SV_OP_BFUNC) {  // branch op: no qubits, one clbit
+            if (op.nq != 0) return fail(SV_EINVAL, "op %zu: branch op takes no qubits", i);
+            if (op.c[0] >= SV_MAX_CLBITS) return fail(SV_EINVAL, "op %zu: clbit %u >= 64", i, op.c[0]);
+            XOp x;
+            x.kind = (int)k;
+            x.rule = -1;
+            x.c.push_back((int)op.c[0]);
+            x.cond_mask = op.cond_mask;
+            x.cond_value = op.cond_value;
+            x.p[0] = x.p[1] = x.p[2] = 0;
+            xo.push_back(x);
+            continue;
+        }
         if (!gate && !meas) return fail(SV_EINVAL, "op %zu: unknown kind %u", i, k);
         const int nq = gate ? gate_nq(k, op.nq) : (int)op.nq;
         if (gate && k != SV_OP_UNITARY && op.nq != (uint32_t)nq && op.nq != 0)
@@ -358,6 +374,8 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
         XOp x;
         x.kind = (int)k;
         x.rule = -1;
+        x.cond_mask = op.cond_mask;
+        x.cond_value = op.cond_value;
         uint64_t seen = 0;
         for (int t = 0; t < nq; ++t) {
             if (qs[t] >= (uint32_t)n) return fail(SV_EINVAL, "op %zu: qubit %u out of range", i, qs[t]);
@@ -401,6 +419,8 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
                 ch.kind = rules[r].kraus ? -2 : -1;
                 ch.rule = (int)r;
                 ch.q = x.q;
+                ch.cond_mask = x.cond_mask;  // noise of a conditional gate is conditional too
+                ch.cond_value = x.cond_value;
                 xo.push_back(ch);
             }
         }
@@ -431,10 +451,13 @@ struct Plan {
     std::vector<uint32_t> op_pass, op_group;  // per device position
 };
 
+// Ops whose effect depends on, or changes, per-shot state beyond their qubits:
+// Kraus channels and measurements (outcome probabilities), conditional ops
+// and branch ops (the classical register).
 static bool op_ordered(const XOp &x)
 {
     return x.kind == -2 || x.kind == SV_OP_MEASURE || x.kind == SV_OP_RESET ||
-           x.kind == SV_OP_MEASURE_RESET;
+           x.kind == SV_OP_MEASURE_RESET || x.kind == SV_OP_BFUNC || x.cond_mask != 0;
 }
 
 static bool op_fallback(const XOp &x, const std::vector<Rule> &rules)
@@ -482,7 +505,7 @@ static size_t unit_end(const std::vector<XOp> &xo, const std::vector<uint32_t> &
 {
     const XOp &g = xo[list[idx]];
     size_t e = idx + 1;
-    if (g.kind < 0 || op_ordered(g) || (groups && op_fallback(g, rules))) return e;
+    if (g.kind < 0 || !is_gate_kind((uint32_t)g.kind) || (groups && op_fallback(g, rules))) return e;
     const uint32_t m = qmask_of(g);
     while (e < list.size() && list[e] == list[e - 1] + 1) {
         const XOp &x = xo[list[e]];
@@ -883,6 +906,7 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
         if (last.kind == SV_OP_MEASURE && (int)last.q.size() == n) {
             terminal = true;
             for (int t = 0; t < n; ++t) terminal = terminal && last.q[t] == t;
+            terminal = terminal && last.cond_mask == 0;
         }
     }
     for (size_t j = 0; j < xo.size(); ++j) {
@@ -898,6 +922,10 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     Plan plan;
     const uint32_t swz = b->dtype == SV_C128 ? 63u : 62u;
     const bool plain = b->mode == SV_MODE_PLAIN;
+    if (plain)
+        for (const XOp &x : xo)
+            if (x.cond_mask != 0 || x.kind == SV_OP_BFUNC)
+                return fail(SV_EUNSUPPORTED, "plain mode runs unconditional circuits only");
     if (plain) {  // list order, one pass and one group holding everything
         PassInfo pi;
         std::memset(&pi, 0, sizeof pi);
@@ -944,7 +972,13 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
                 if (gi.gpos[a] == d.lb[t]) rb = a;
             d.rb[t] = (uint8_t)rb;
         }
-        if (x.kind == -1 || x.kind == -2) {
+        d.cond_mask = x.cond_mask;
+        d.cond_value = x.cond_value;
+        if (x.cond_mask != 0 && x.kind != SV_OP_BFUNC) d.flags |= DF_COND;
+        if (x.kind == SV_OP_BFUNC) {
+            d.kind = DK_BFUNC;
+            d.c[0] = (uint8_t)x.c[0];
+        } else if (x.kind == -1 || x.kind == -2) {
             d.kind = x.kind == -1 ? DK_PAULI : DK_KRAUS;
             d.rule = (uint32_t)x.rule;
         } else if (x.kind == SV_OP_CX) {
@@ -1201,6 +1235,7 @@ sv_status svb_debug_plan(int n_qubits, int tile_q, int reg_bits, const sv_op *op
         if (last.kind == SV_OP_MEASURE && (int)last.q.size() == n_qubits) {
             terminal = true;
             for (int t = 0; t < n_qubits; ++t) terminal = terminal && last.q[t] == t;
+            terminal = terminal && last.cond_mask == 0;
         }
     }
     const bool resident = n_qubits <= tile_q;

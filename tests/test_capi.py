@@ -67,6 +67,9 @@ def _run_unattached(circ, noise, n=3, shots=4):
     {"kind": "cx", "qubits": [1, 1]},                                # repeated qubit
     {"kind": "measure", "qubits": [0], "clbits": [64]},              # clbit >= 64
     {"kind": "unitary", "qubits": [0], "matrix": [[1, 1], [0, 1]]},  # not unitary
+    {"kind": "x", "qubits": [0], "cond": [1, 2]},                    # value outside mask
+    {"kind": "bfunc", "qubits": [0], "clbits": [1], "mask": 1, "value": 1},  # branch op with qubits
+    {"kind": "bfunc", "clbits": [64], "mask": 1, "value": 0},       # branch-op clbit >= 64
 ])
 def test_invalid_ops_are_rejected_without_device(bad):
     circ = {"n_qubits": 3, "n_clbits": 1, "ops": [bad]}

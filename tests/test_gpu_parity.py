@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+import paper_2308_03399_amd as S
 import workloads as W
 from gpu_util import gpu_run, mismatches, oracle_memory, say, tvd_counts
 
@@ -245,3 +246,49 @@ def test_qft_workload_matches_oracle(form, mode, n, tile):
     got = gpu_run(circ, noise, shots, dtype="c128", mode=mode, seed=11, **opts)
     exp = oracle_memory(circ, noise, shots, seed=11)
     assert mismatches(got["memory"], exp) == 0
+
+
+# ---------------------------------------------------------------------------
+# Conditional operations and branch ops on the classical register (Sec. IV-A)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,mode,tile,dtype", [(3, "batch", 0, "c128"), (6, "branch", 0, "c128"),
+                                               (14, "batch", 12, "c128"), (14, "branch", 12, "c128"),
+                                               (14, "batch", 13, "c64")])
+def test_conditional_circuits_match_oracle(n, mode, tile, dtype):
+    circ = W.random_small(n, 60, seed=31 + n, n_mid=5, p_cond=0.5)
+    assert sum(1 for op in circ["ops"] if op.get("cond")) >= 3
+    noise = _noise_full(p1=0.05, p2=0.08, gamma=0.05)   # readout flips make cregs differ
+    shots = 128
+    say(f"case conditional n={n} mode={mode} tile={tile} dtype={dtype}")
+    opts = {"tile_qubits": tile} if tile else {}
+    got = gpu_run(circ, noise, shots, dtype=dtype, mode=mode, seed=13, **opts)
+    exp = oracle_memory(circ, noise, shots, seed=13)
+    bad = mismatches(got["memory"], exp)
+    assert bad == 0 if dtype == "c128" else bad <= 1
+
+
+def test_feed_forward_in_branch_mode_splits_by_register():
+    # H, measure q0 -> c0, X on q1 iff c0 == 1, branch op c2 = (c0 == 1),
+    # Z on q0 iff c2 == 1, final measure of both
+    ops = [{"kind": "h", "qubits": [0]},
+           {"kind": "measure", "qubits": [0], "clbits": [0]},
+           {"kind": "x", "qubits": [1], "cond": [1, 1]},
+           {"kind": "bfunc", "clbits": [2], "mask": 1, "value": 1},
+           {"kind": "z", "qubits": [0], "cond": [4, 4]},
+           {"kind": "measure", "qubits": [0, 1], "clbits": [0, 1]}]
+    circ = {"n_qubits": 2, "n_clbits": 3, "ops": ops}
+    noise = W.noise_model([], readout=(0.1, 0.1))
+    shots = 512
+    say("case feed-forward branch")
+    got = gpu_run(circ, noise, shots, dtype="c128", mode="branch", seed=3)
+    exp = oracle_memory(circ, noise, shots, seed=3)
+    assert mismatches(got["memory"], exp) == 0
+
+
+def test_plain_mode_refuses_conditional_circuits():
+    circ = {"n_qubits": 2, "n_clbits": 1,
+            "ops": [{"kind": "measure", "qubits": [0], "clbits": [0]},
+                    {"kind": "x", "qubits": [1], "cond": [1, 1]}]}
+    with pytest.raises(S.SvError) as e:
+        gpu_run(circ, None, 4, dtype="c128", mode="plain")
+    assert e.value.status == 5

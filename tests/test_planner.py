@@ -41,10 +41,10 @@ def _plan(circ, noise, tile_q, reg_bits):
 
 def _is_ordered_random(x):
     return (x["kind"] == "channel" and x["rule"]["type"] == "kraus") or \
-        x["kind"] in ("measure", "reset", "measure_reset")
+        x["kind"] in ("measure", "reset", "measure_reset", "bfunc") or bool(x.get("cond"))
 
 
-@pytest.mark.parametrize("case", ["c3", "c2", "small"])
+@pytest.mark.parametrize("case", ["c3", "c2", "small", "cond"])
 @pytest.mark.parametrize("tile_q,reg_bits", [(13, 5), (14, 6), (12, 4), (8, 0)])
 def test_plan_respects_dependencies(case, tile_q, reg_bits):
     if case == "c3":
@@ -54,6 +54,10 @@ def test_plan_respects_dependencies(case, tile_q, reg_bits):
     elif case == "c2":
         w = W.workload("c2_16q")
         circ, noise = w["circuit"], w["noise"]
+    elif case == "cond":
+        circ = W.random_small(16, 300, seed=6, n_mid=8, p_cond=0.3)
+        noise = W.noise_model([W.rule(["u3", "h"], W.amplitude_damping_kraus(0.1)),
+                               W.rule(["cx", "cz"], W.depolarizing_pauli(0.1, 2))])
     else:
         circ = W.random_small(16, 300, seed=5, n_mid=6)
         noise = W.noise_model([W.rule(["u3", "h"], W.amplitude_damping_kraus(0.1)),
@@ -66,7 +70,7 @@ def test_plan_respects_dependencies(case, tile_q, reg_bits):
     last_on_qubit = {}
     last_random = -1
     for j, x in enumerate(xo):
-        for q in x["qubits"]:
+        for q in x.get("qubits", []):
             if q in last_on_qubit:
                 assert pos[last_on_qubit[q]] < pos[j], ("qubit order", q, j)
             last_on_qubit[q] = j
@@ -79,8 +83,8 @@ def test_plan_respects_dependencies(case, tile_q, reg_bits):
     for p, m in enumerate(pmask):
         assert bin(int(m)).count("1") == k
     for d, j in enumerate(order):
-        qm = sum(1 << q for q in xo[j]["qubits"])
-        if len(xo[j]["qubits"]) < n:  # the final measure-all has its own pass
+        qm = sum(1 << q for q in xo[j].get("qubits", []))
+        if len(xo[j].get("qubits", [])) < n:  # the final measure-all has its own pass
             assert (qm & ~int(pmask[opass[d]])) == 0
         if reg_bits > 0 and n > tile_q:
             assert gw[ogrp[d]] <= reg_bits
