@@ -292,3 +292,40 @@ def test_plain_mode_refuses_conditional_circuits():
     with pytest.raises(S.SvError) as e:
         gpu_run(circ, None, 4, dtype="c128", mode="plain")
     assert e.value.status == 5
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads, in the launch shapes the benchmark uses; the oracle
+# checks sampled shot ids one by one
+# ---------------------------------------------------------------------------
+def test_c2_full_size_sampled_shots():
+    w = W.workload("c2_16q")
+    shots = w["shots"]
+    say(f"case c2 16q x 40 layers with mid-circuit measure+reset, {shots} shots c128")
+    got = gpu_run(w["circuit"], w["noise"], shots, dtype="c128", seed=w["seed"])
+    ids = list(range(128)) + list(range(shots - 128, shots))
+    exp = oracle.run(w["circuit"], w["noise"], ids, seed=w["seed"])
+    assert mismatches(np.asarray(got["memory"])[ids], exp) == 0
+    say("case c2 c64")
+    got64 = gpu_run(w["circuit"], w["noise"], shots, dtype="c64", seed=w["seed"])
+    agree = float(np.mean(np.asarray(got64["memory"])[ids] == exp))
+    assert agree >= 0.99
+    assert tvd_counts(got64["memory"], got["memory"]) <= 0.03   # sampling noise at 10k shots
+
+
+def test_c3_full_size_sampled_shots():
+    # one benchmark wave: 10,000 shots of the 20-qubit, 60-layer workload in
+    # complex64 with the default launch shape; oracle on its first and last ids
+    w = W.workload("c3_20q")
+    shots = 10_000
+    say(f"case c3 20q x 60 layers, {shots} shots c64 (one benchmark wave)")
+    got = gpu_run(w["circuit"], w["noise"], shots, dtype="c64", seed=w["seed"])
+    ids = list(range(8)) + list(range(shots - 8, shots))
+    exp = oracle.run(w["circuit"], w["noise"], ids, seed=w["seed"])
+    agree = int(np.sum(np.asarray(got["memory"])[ids] == exp))
+    assert agree >= len(ids) - 1
+    say("case c3 c128, 512 shots")
+    got128 = gpu_run(w["circuit"], w["noise"], 512, dtype="c128", seed=w["seed"])
+    ids128 = list(range(4)) + list(range(508, 512))
+    exp128 = oracle.run(w["circuit"], w["noise"], ids128, seed=w["seed"])
+    assert mismatches(np.asarray(got128["memory"])[ids128], exp128) == 0
