@@ -200,6 +200,20 @@ sv_status sv_batch_attach(sv_batch *b, void *device_arena, uint64_t arena_bytes,
 sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops,
                          const sv_noise_model *nm, uint64_t seed);
 
+/* Parameter sweep in one launch: n_sets circuits that differ only in the
+ * angles of their U3 gates (the batched execution of Sec. IV-A, with the
+ * per-state gate parameters of its parameter buffers varying by set).
+ * params holds n_sets rows of 3 * n_u3 doubles, (theta, phi, lambda) of each
+ * U3 op of ops[] in order; the p[] of those ops is ignored. The run's shots
+ * are split evenly: set s owns shot ids [s*S/n_sets, (s+1)*S/n_sets), and
+ * each of those shots is exactly the shot of sv_run_circuit on the circuit
+ * with set s's angles. Batch mode only (SV_EUNSUPPORTED otherwise);
+ * SV_EINVAL if n_sets is 0 or does not divide the shot count. Results as for
+ * sv_run_circuit (memory in shot order, counts over all sets). */
+sv_status sv_run_sweep(sv_batch *b, const sv_op *ops, size_t n_ops,
+                       const sv_noise_model *nm, uint64_t seed,
+                       const double *params, size_t n_sets);
+
 /* Bit-count histogram of the last run (Sec. III-B): keys[i] is a classical
  * register value (clbit c <-> bit c), counts[i] its number of shots, keys
  * ascending. If capacity < the number of distinct keys, *n_unique receives

@@ -30,7 +30,7 @@ PAULI_CODE = {"I": 0, "X": 1, "Y": 2, "Z": 3}
 MAX_INLINE = 8
 
 EXPORTED = ["sv_batch_create", "sv_batch_footprint", "sv_batch_attach",
-            "sv_batch_set_option", "sv_run_circuit", "sv_sample_counts",
+            "sv_batch_set_option", "sv_run_circuit", "sv_run_sweep", "sv_sample_counts",
             "sv_get_memory", "sv_get_state", "sv_get_stats",
             "sv_batch_destroy", "sv_last_error"]
 
@@ -116,6 +116,8 @@ def lib() -> ctypes.CDLL:
     L.sv_batch_set_option.argtypes = [P, ctypes.c_char_p, I64]
     L.sv_run_circuit.argtypes = [P, ctypes.POINTER(sv_op), ctypes.c_size_t,
                                  ctypes.POINTER(sv_noise_model), U64]
+    L.sv_run_sweep.argtypes = [P, ctypes.POINTER(sv_op), ctypes.c_size_t,
+                               ctypes.POINTER(sv_noise_model), U64, P, ctypes.c_size_t]
     L.sv_sample_counts.argtypes = [P, P, P, ctypes.c_size_t,
                                    ctypes.POINTER(ctypes.c_size_t)]
     L.sv_get_memory.argtypes = [P, P, ctypes.c_size_t]
@@ -161,6 +163,15 @@ def sv_batch_attach(h: int, arena_ptr: int, arena_bytes: int, stream: int):
 def sv_run_circuit(h: int, marshalled, seed: int):
     ops, n_ops, nm = marshalled["ops"], marshalled["n_ops"], marshalled["nm"]
     _check(lib().sv_run_circuit(h, ops, n_ops, nm, int(seed)))
+
+
+def sv_run_sweep(h: int, marshalled, seed: int, params) -> None:
+    """params: array (n_sets, n_u3, 3) of U3 angles, one row per set."""
+    ops, n_ops, nm = marshalled["ops"], marshalled["n_ops"], marshalled["nm"]
+    a = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    if a.ndim != 3 or a.shape[2] != 3:
+        raise ValueError("params must have shape (n_sets, n_u3, 3)")
+    _check(lib().sv_run_sweep(h, ops, n_ops, nm, int(seed), a.ctypes.data, a.shape[0]))
 
 
 def sv_sample_counts(h: int, capacity: int = 0) -> Dict[int, int]:
@@ -306,6 +317,11 @@ class Simulator:
         m = marshal(circuit, noise)
         with self.torch.cuda.device(self.device):
             sv_run_circuit(self.h, m, seed)
+
+    def run_sweep(self, circuit: Dict, noise: Optional[Dict], params, seed: int = 0):
+        m = marshal(circuit, noise)
+        with self.torch.cuda.device(self.device):
+            sv_run_sweep(self.h, m, seed, params)
 
     def counts(self, capacity: int = 0) -> Dict[int, int]:
         return sv_sample_counts(self.h, capacity or self.n_shots)

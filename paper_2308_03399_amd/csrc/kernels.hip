@@ -261,6 +261,16 @@ __device__ __forceinline__ double uni(double v)
     return __builtin_bit_cast(double, lo | (hi << 32));
 }
 
+// Matrix of a one-qubit gate op for the record's shot: a swept U3 takes its
+// set's matrix (sets split the run's shots evenly; batch mode, one shot).
+__device__ __forceinline__ const double *op_matrix(const ExecParams &P, const DevOp &op,
+                                                   const lds<WgShared> &S)
+{
+    if (!(op.flags & DF_PARAM)) return P.pool + op.mat;
+    const uint32_t set = (uint32_t)P.shot_perm[S.lo] / P.shots_per_set;
+    return P.pool + op.mat + (size_t)set * P.set_stride;
+}
+
 __device__ __forceinline__ UOp get_uop(const lds<UOp> *p)
 {
     const uint64_t w = *(const lds<uint64_t> *)p;
@@ -504,7 +514,7 @@ __device__ __noinline__ void apply_op(Ctx<R> &c, const DevOp &op, int d, double 
     if (op.kind == DK_BFUNC || ((op.flags & DF_COND) && d == kSkip)) return;
     switch (op.kind) {
     case DK_MAT1: {
-        const Mat2<R> m = load_m2<R>(P.pool + op.mat, 1.0);
+        const Mat2<R> m = load_m2<R>(op_matrix(P, op, c.S), 1.0);
         sweep_mat1(c, op.lb[0], m, (op.flags & DF_DIAG) != 0);
         break;
     }
@@ -981,7 +991,7 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
             if (op.kind == DK_BFUNC || ((op.flags & DF_COND) && d == kSkip)) continue;
             switch (op.kind) {
             case DK_MAT1:
-                fuse_factor(c, op.rb[0], P.pool + op.mat, 1.0, pend_set);
+                fuse_factor(c, op.rb[0], op_matrix(P, op, S), 1.0, pend_set);
                 break;
             case DK_KRAUS: {
                 const DevRule &ru = P.rules[op.rule];

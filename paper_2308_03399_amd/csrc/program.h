@@ -40,6 +40,7 @@ enum DevFlags : uint8_t {
     DF_RESET = 4,     // DK_MEASURE: return measured 1s to |0>
     DF_TERMINAL = 8,  // DK_MEASURE: last op, all qubits in order (sampling)
     DF_COND = 16,     // runs only for shots with (creg & cond_mask) == cond_value
+    DF_PARAM = 32,    // DK_MAT1 of a swept U3: matrix of set s at mat + s * set_stride
 };
 
 struct DevOp {
@@ -164,6 +165,8 @@ struct ExecParams {
     int32_t resident;        // 1: whole state in LDS (n <= k)
     int32_t use_groups;      // 1: streamed passes run register groups
     uint32_t swz;            // LDS swizzle mask of streamed passes
+    uint32_t set_stride;     // parameter sweep: pool doubles between sets (0: none)
+    uint32_t shots_per_set;  // parameter sweep: shots of each set
     int32_t nbuf;            // LDS tile buffers of streamed grouped passes (1, or 2:
                              // the next tile is fetched while this one computes)
 };

@@ -224,6 +224,7 @@ static void layout(sv_batch *b)
 struct XOp {  // expanded op
     int kind;       // sv_op_kind, or -1 Pauli channel, -2 Kraus channel
     int rule;
+    int u3_index = -1;  // U3 ops: their index among the circuit's U3 ops
     uint64_t cond_mask = 0, cond_value = 0;  // condition (BFUNC: its predicate)
     std::vector<int> q, c;
     double p[3];
@@ -340,6 +341,7 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
     }
     xo.clear();
     gate_count = 0;
+    int n_u3 = 0;
     int terminal_seen = 0;
     for (size_t i = 0; i < n_ops; ++i) {
         const sv_op &op = ops[i];
@@ -374,6 +376,7 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
         XOp x;
         x.kind = (int)k;
         x.rule = -1;
+        if (k == SV_OP_U3) x.u3_index = n_u3++;
         x.cond_mask = op.cond_mask;
         x.cond_value = op.cond_value;
         uint64_t seen = 0;
@@ -883,11 +886,18 @@ sv_status sv_batch_attach(sv_batch *b, void *arena, uint64_t bytes, void *stream
     return SV_OK;
 }
 
-sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_noise_model *nm,
-                         uint64_t seed)
+static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_noise_model *nm,
+                          uint64_t seed, const double *params, size_t n_sets)
 {
     if (!b) return fail(SV_EINVAL, "NULL handle");
     if (!ops && n_ops) return fail(SV_EINVAL, "ops is NULL");
+    const bool sweep = params != nullptr;
+    if (sweep) {
+        if (b->mode != SV_MODE_BATCH) return fail(SV_EUNSUPPORTED, "parameter sweeps run in batch mode");
+        if (n_sets == 0 || b->shots % (int64_t)n_sets != 0)
+            return fail(SV_EINVAL, "n_sets %zu must divide the %lld shots", n_sets, (long long)b->shots);
+        if ((uint64_t)b->shots / n_sets > 0xffffffffull) return fail(SV_EINVAL, "too many shots per set");
+    }
     b->have_results = false;
     b->have_dump = false;
     std::vector<Rule> rules;
@@ -996,6 +1006,10 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
                 d.nq = (uint8_t)n;
             }
             for (size_t t = 0; t < x.c.size() && t < 32; ++t) d.c[t] = (uint8_t)x.c[t];
+        } else if (sweep && x.u3_index >= 0) {
+            d.kind = DK_MAT1;
+            d.flags |= DF_PARAM;       // matrices of every set follow the base pool
+            d.mat = (uint32_t)(x.u3_index * 8);  // rebased below
         } else {
             d.kind = x.q.size() == 1 ? DK_MAT1 : DK_MAT2;
             d.mat = (uint32_t)pool.size();
@@ -1006,6 +1020,24 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
                 pool.push_back(v.imag());
             }
         }
+    }
+    uint32_t set_stride = 0;
+    if (sweep) {
+        int n_u3 = 0;
+        for (const XOp &x : xo) n_u3 = std::max(n_u3, x.u3_index + 1);
+        set_stride = (uint32_t)(n_u3 * 8);
+        const uint64_t block = pool.size();
+        if (block + (uint64_t)set_stride * n_sets > 0xffffffffull) return fail(SV_EINVAL, "sweep too large");
+        for (size_t st = 0; st < n_sets; ++st)
+            for (int u = 0; u < n_u3; ++u) {
+                const double *a = params + (st * (size_t)n_u3 + u) * 3;
+                for (const cd &v : gate_1q(SV_OP_U3, a)) {
+                    pool.push_back(v.real());
+                    pool.push_back(v.imag());
+                }
+            }
+        for (DevOp &d : dops)
+            if (d.flags & DF_PARAM) d.mat += (uint32_t)block;
     }
     if (pool.empty()) pool.push_back(0);
     // upload program
@@ -1066,6 +1098,8 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     P.use_groups = b->use_groups;
     P.swz = swz;
     P.nbuf = b->nbuf;
+    P.set_stride = set_stride;
+    P.shots_per_set = sweep ? (uint32_t)((uint64_t)b->shots / n_sets) : 1u;
 
     if (plain) {
         double *scratch = (double *)(A + L.tile_sums);
@@ -1155,6 +1189,19 @@ sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_n
     b->have_results = true;
     b->have_dump = b->dump_shot >= 0;
     return SV_OK;
+}
+
+sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_noise_model *nm,
+                         uint64_t seed)
+{
+    return run_impl(b, ops, n_ops, nm, seed, nullptr, 1);
+}
+
+sv_status sv_run_sweep(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_noise_model *nm,
+                       uint64_t seed, const double *params, size_t n_sets)
+{
+    if (!params) return fail(SV_EINVAL, "params is NULL");
+    return run_impl(b, ops, n_ops, nm, seed, params, n_sets);
 }
 
 sv_status sv_sample_counts(sv_batch *b, uint64_t *keys, uint64_t *counts, size_t capacity,

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_2308_03399_amd as S
@@ -122,3 +123,19 @@ def test_large_mid_circuit_measure_is_unsupported():
         _run_unattached(circ, None, n=6)
     # validation of sizes happens before the arena check
     assert e.value.status == 5
+
+
+def test_sweep_argument_checks_without_device():
+    circ = {"n_qubits": 2, "n_clbits": 0, "ops": [{"kind": "u3", "qubits": [0], "params": [0, 0, 0]}]}
+    params = np.zeros((3, 1, 3))
+    h = S.sv_batch_create(2, 10, S.SV_C128)
+    try:
+        with pytest.raises(S.SvError) as e:       # 3 sets do not divide 10 shots
+            S.sv_run_sweep(h, S.marshal(circ, None), 0, params)
+        assert e.value.status == 1
+        S.sv_batch_set_option(h, "mode", S.SV_MODE_BRANCH)
+        with pytest.raises(S.SvError) as e:       # sweeps run in batch mode only
+            S.sv_run_sweep(h, S.marshal(circ, None), 0, np.zeros((2, 1, 3)))
+        assert e.value.status == 5
+    finally:
+        S.sv_batch_destroy(h)

@@ -329,3 +329,39 @@ def test_c3_full_size_sampled_shots():
     ids128 = list(range(4)) + list(range(508, 512))
     exp128 = oracle.run(w["circuit"], w["noise"], ids128, seed=w["seed"])
     assert mismatches(np.asarray(got128["memory"])[ids128], exp128) == 0
+
+
+# ---------------------------------------------------------------------------
+# Parameter sweeps: circuits differing only in U3 angles, one launch
+# ---------------------------------------------------------------------------
+def _with_angles(circ, angles):
+    ops, u = [], 0
+    for op in circ["ops"]:
+        if op["kind"] == "u3":
+            op = dict(op, params=[float(x) for x in angles[u]])
+            u += 1
+        ops.append(op)
+    return dict(circ, ops=ops)
+
+
+@pytest.mark.parametrize("n,dtype,tile", [(8, "c128", 0), (15, "c128", 12), (15, "c64", 13)])
+def test_parameter_sweep_matches_oracle_per_set(n, dtype, tile):
+    circ = W.random_layered(n, 4, seed=17, mid_measure=(2, (0,)))
+    noise = _noise_full(p1=0.03, p2=0.05, gamma=0.04)
+    n_u3 = sum(1 for op in circ["ops"] if op["kind"] == "u3")
+    n_sets, per = 4, 24
+    params = np.random.default_rng(5).uniform(0, 2 * math.pi, (n_sets, n_u3, 3))
+    say(f"case sweep n={n} dtype={dtype} tile={tile} sets={n_sets}")
+    opts = {"tile_qubits": tile} if tile else {}
+    sim = S.Simulator(n, n_sets * per, dtype=dtype, spin_limit_ms=60000, **opts)
+    try:
+        sim.run_sweep(circ, noise, params, seed=8)
+        mem = sim.memory()
+    finally:
+        sim.close()
+    bad = 0
+    for s in range(n_sets):
+        ids = list(range(s * per, (s + 1) * per))
+        exp = oracle.run(_with_angles(circ, params[s]), noise, ids, seed=8)
+        bad += mismatches(np.asarray(mem)[ids], exp)
+    assert bad == 0 if dtype == "c128" else bad <= 2
