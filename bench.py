@@ -27,9 +27,10 @@ FP64_VECTOR_PEAK_TF = 78.6
 
 
 def kernel_source_hash() -> str:
+    """Hash of the executor's source and of the build script (its flags)."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "program.h"):
-        with open(os.path.join(ROOT, "paper_2308_03399_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/kernels.hip", "csrc/program.h", "build.py"):
+        with open(os.path.join(ROOT, "paper_2308_03399_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -109,6 +110,84 @@ def qft_comparison(n, shots=4000, p=0.01, plain_shots=40):
         print(json.dumps(line), flush=True)
 
 
+def serving_bench(n_requests: int, load: float = 0.8, max_active: int = 4):
+    """Serving workload: the seeded Poisson stream of random noisy U3+CX
+    circuits (qubits U{8..24}, depth U{10..60}, shots log-uniform in
+    [100, 1e5], depolarizing 1e-3 / 1e-2, complex64), its first n_requests.
+    First all requests at once (closed loop: capacity), then the same
+    requests with Poisson arrivals at `load` x that capacity (latency)."""
+    import workloads as W
+    import paper_2308_03399_amd.serving as SV
+
+    def requests(rate):
+        stream = W.serving_stream(n_requests, rate, seed=0)
+        reqs = [SV.Request(circuit=r["circuit"], noise=r["noise"], shots=r["shots"],
+                           seed=r["seed"], dtype=r["dtype"], mode="batch", id=r["id"])
+                for r in stream]
+        return reqs, [r["arrival_s"] for r in stream]
+
+    def log(tag, rep):
+        for res in rep["results"]:
+            print(f"[serve {tag}] request {res.id}: {res.shots} shots, "
+                  f"{len(res.chunks)} chunks, latency {res.latency:.3f} s",
+                  file=sys.stderr, flush=True)
+
+    reqs, _ = requests(1.0)
+    # warm-up: first request only (library load, kernel modules)
+    with SV.Server(max_active=max_active) as srv:
+        srv.submit(SV.Request(circuit=reqs[0].circuit, noise=reqs[0].noise,
+                              shots=min(reqs[0].shots, 256), seed=0)).wait()
+    with SV.Server(max_active=max_active) as srv:
+        closed = SV.replay(srv, reqs, [0.0] * len(reqs))
+    log("closed", closed)
+    cap = closed["requests_per_s"]
+    reqs, arrivals = requests(load * cap)
+    with SV.Server(max_active=max_active) as srv:
+        open_ = SV.replay(srv, reqs, arrivals)
+    log("poisson", open_)
+    work = sum(r.shots * r.gates for r in open_["results"])
+
+    def summary(rep):
+        return {"makespan_s": round(rep["makespan_s"], 3),
+                "shots_gates_per_s": rep["shots_gates_per_s"],
+                "requests_per_s": round(rep["requests_per_s"], 4),
+                "p50_latency_s": round(rep["p50_s"], 4),
+                "p99_latency_s": round(rep["p99_s"], 4),
+                "mean_latency_s": round(rep["mean_s"], 4),
+                "peak_arena_bytes": rep["peak_bytes"]}
+
+    out = {
+        "metric": "serving: shots×gates/s with p50/p99 latency, Poisson stream of noisy circuits",
+        "value": open_["shots_gates_per_s"],
+        "unit": "shots*gates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": open_["makespan_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"c5_serving: first {n_requests} requests of the seed-0 Poisson "
+                        "stream; qubits U{8..24}, depth U{10..60}, shots log-uniform "
+                        "[100, 1e5]; depolarizing 1e-3 / 1e-2; batch mode",
+            "requests": [{"id": r.id, "qubits": r.circuit["n_qubits"], "shots": r.shots,
+                          "gates": r.gates, "latency_s": round(r.latency, 4),
+                          "chunks": len(r.chunks)} for r in open_["results"]],
+            "total_shots_gates": work,
+            "max_active": max_active,
+            "arrival_rate_per_s": round(load * cap, 5),
+            "load": load,
+        },
+        "serving": {"poisson": summary(open_), "closed_loop": summary(closed)},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +204,9 @@ def main():
     ap.add_argument("--qft", type=str, default="",
                     help="instead of the headline workload: the paper's QFT comparison, "
                          "comma-separated qubit counts (4000 shots, 1%% noise)")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="instead of the headline workload: the serving stream, this many "
+                         "requests (closed loop, then Poisson at 0.8x its capacity)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: shots shard across GPUs by "
@@ -136,6 +218,9 @@ def main():
     import workloads as W
     from paper_2308_03399_amd import Simulator
 
+    if args.serve:
+        serving_bench(args.serve)
+        return
     if args.qft:
         for n in [int(x) for x in args.qft.split(",")]:
             qft_comparison(n)

@@ -139,3 +139,28 @@ def test_sweep_argument_checks_without_device():
         assert e.value.status == 5
     finally:
         S.sv_batch_destroy(h)
+
+
+def test_executor_keeps_two_waves_per_simd():
+    """The build records hipcc's resource usage of the executor kernels.
+    The instantiations that run two workgroups per compute unit must fit
+    two waves per SIMD in the unified register file."""
+    import json
+    from paper_2308_03399_amd import build as B
+    if not os.path.exists(B.RESOURCES):
+        pytest.skip("library not built")
+    with open(B.RESOURCES) as f:
+        res = json.load(f)
+    for k in B.TWO_WAVE_KERNELS:
+        assert res[k]["Occupancy [waves/SIMD]"] >= 2, (k, res[k])
+        assert res[k]["VGPRs"] + res[k].get("AGPRs", 0) <= 256, (k, res[k])
+
+
+def test_resource_remarks_are_parsed():
+    from paper_2308_03399_amd import build as B
+    text = ("x.hip:1:1: remark: Function Name: _Zfoo [-Rpass-analysis=kernel-resource-usage]\n"
+            "x.hip:1:1: remark:     VGPRs: 200 [-Rpass-analysis=kernel-resource-usage]\n"
+            "x.hip:1:1: remark:     AGPRs: 0 [-Rpass-analysis=kernel-resource-usage]\n"
+            "x.hip:1:1: remark:     Occupancy [waves/SIMD]: 2 [-Rpass-analysis=kernel-resource-usage]\n")
+    r = B.parse_resource_usage(text)
+    assert r == {"_Zfoo": {"VGPRs": 200, "AGPRs": 0, "Occupancy [waves/SIMD]": 2}}
