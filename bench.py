@@ -173,7 +173,7 @@ def serving_bench(n_requests: int, load: float = 0.8, max_active: int = 4):
             "workload": f"c5_serving: first {n_requests} requests of the seed-0 Poisson "
                         "stream; qubits U{8..24}, depth U{10..60}, shots log-uniform "
                         "[100, 1e5]; depolarizing 1e-3 / 1e-2; batch mode",
-            "requests": [{"id": r.id, "qubits": r.circuit["n_qubits"], "shots": r.shots,
+            "requests": [{"id": r.id, "qubits": r.n_qubits, "shots": r.shots,
                           "gates": r.gates, "latency_s": round(r.latency, 4),
                           "chunks": len(r.chunks)} for r in open_["results"]],
             "total_shots_gates": work,

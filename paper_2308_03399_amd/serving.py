@@ -85,6 +85,7 @@ class Result:
     counts: Dict[int, int]
     gates: int
     shots: int
+    n_qubits: int
     t_submit: float
     t_start: float
     t_done: float
@@ -202,6 +203,7 @@ class Server:
         self._running = 0
         self._used = 0
         self._peak_used = 0
+        self._fp_cache: Dict = {}
         self._mem_queue: collections.deque = collections.deque()  # chunks waiting for bytes
         self._closed = False
         self._threads = [threading.Thread(target=self._runner, daemon=True,
@@ -272,7 +274,7 @@ class Server:
         cands = [workers]
         while cands[-1] > 1:
             cands.append(max(1, cands[-1] // 2))
-        sizes = [(w, self.backend.footprint(req, n_shots, w)) for w in cands]
+        sizes = [(w, self._footprint(req, n_shots, w)) for w in cands]
         if sizes[-1][1] > self.budget:
             raise MemoryError(f"request {req.id}: one state needs {sizes[-1][1]} bytes, "
                               f"budget {self.budget}")
@@ -292,6 +294,16 @@ class Server:
             finally:
                 self._mem_queue.remove(token)
                 self._cv.notify_all()
+
+    def _footprint(self, req: Request, n_shots: int, workers: int) -> int:
+        """Arena bytes of a chunk shape, computed once per shape."""
+        key = (req.circuit["n_qubits"], req.dtype, req.mode,
+               tuple(sorted(req.options.items())), n_shots, workers)
+        b = self._fp_cache.get(key)
+        if b is None:
+            b = self.backend.footprint(req, n_shots, workers)
+            self._fp_cache[key] = b
+        return b
 
     def _release(self, nbytes: int):
         with self._cv:
@@ -331,7 +343,7 @@ class Server:
         keys, cnt = np.unique(mem, return_counts=True)
         return Result(id=req.id, memory=mem,
                       counts={int(k): int(v) for k, v in zip(keys, cnt)},
-                      gates=gates, shots=req.shots, t_submit=ticket.t_submit,
+                      gates=gates, shots=req.shots, n_qubits=n, t_submit=ticket.t_submit,
                       t_start=t_start, t_done=time.perf_counter(), chunks=chunks)
 
 
