@@ -160,3 +160,22 @@ def test_replay_reports_latency_and_throughput():
     assert rep["p50_s"] <= rep["p99_s"]
     assert rep["makespan_s"] >= 0.03
     assert rep["shots_gates_per_s"] == pytest.approx(4 * 20 * 5 / rep["makespan_s"])
+
+
+class FailingBackend(FakeBackend):
+    def run(self, req, prepared, offset, n_shots, workers, arena_bytes, stream):
+        if req.id == 1:
+            raise RuntimeError("device executor failed")
+        return super().run(req, prepared, offset, n_shots, workers, arena_bytes, stream)
+
+
+def test_a_failing_request_does_not_stop_the_others():
+    fb = FailingBackend(capacity=4)
+    with SV.Server(max_active=2, hbm_bytes=10_000, backend=fb) as s:
+        tickets = [s.submit(_req(i, 40)) for i in range(4)]
+        with pytest.raises(RuntimeError):
+            tickets[1].wait(30)
+        for i in (0, 2, 3):
+            assert np.array_equal(tickets[i].wait(30).memory, _expected(tickets[i].request.seed, 0, 40))
+        # every reservation was returned
+        assert s._used == 0
