@@ -196,7 +196,9 @@ sv_status sv_batch_attach(sv_batch *b, void *device_arena, uint64_t arena_bytes,
  * distinct within an op, clbits < 64, probabilities, Kraus completeness):
  * SV_EINVAL without touching the device. Blocks until the device work of
  * the run has finished. On any failure the handle is left in a state where
- * results are unavailable until the next successful run. */
+ * results are unavailable until the next successful run. A circuit without
+ * ops (n_ops == 0) is valid: every shot's register is 0 and the state stays
+ * |0..0>. */
 sv_status sv_run_circuit(sv_batch *b, const sv_op *ops, size_t n_ops,
                          const sv_noise_model *nm, uint64_t seed);
 

@@ -886,6 +886,46 @@ sv_status sv_batch_attach(sv_batch *b, void *arena, uint64_t bytes, void *stream
     return SV_OK;
 }
 
+// A circuit without ops: every shot keeps the all-zero register and the
+// state stays |0..0>. Only the initialisation kernel runs (it clears the
+// per-shot registers); a requested state dump is written as |0..0>.
+static sv_status run_empty(sv_batch *b)
+{
+    char *A = b->arena;
+    const auto &L = b->lay;
+    ExecParams P;
+    std::memset(&P, 0, sizeof P);
+    P.memory = (uint64_t *)(A + L.memory);
+    P.shot_perm = (int32_t *)(A + L.perm);
+    P.queue = (BranchRec *)(A + L.queue);
+    P.ready = (uint32_t *)(A + L.ready);
+    P.ctl = (Control *)(A + L.ctl);
+    P.free_slots = (int32_t *)(A + L.free_slots);
+    P.n_shots = b->shots;
+    P.queue_cap = (int32_t)b->shots;
+    HIPCHK(hipEventRecord(b->ev0, b->stream));
+    HIPCHK(svb_launch_init(&P, 0, (int)b->shots, -1, 0, b->stream));
+    if (b->dump_shot >= 0) {
+        static const double one = 1.0;
+        HIPCHK(hipMemsetAsync(A + L.dump, 0, 16ull << b->n, b->stream));
+        HIPCHK(hipMemcpyAsync(A + L.dump, &one, sizeof one, hipMemcpyHostToDevice, b->stream));
+    }
+    HIPCHK(hipEventRecord(b->ev1, b->stream));
+    HIPCHK(hipEventSynchronize(b->ev1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    sv_stats &st = b->stats;
+    std::memset(&st, 0, sizeof st);
+    st.kernel_ms = ms;
+    st.workers = (uint32_t)b->workers;
+    st.slots = (uint32_t)b->slots;
+    st.tile_qubits = (uint32_t)b->tile_q;
+    st.tile_buffers = (uint32_t)b->nbuf;
+    b->have_results = true;
+    b->have_dump = b->dump_shot >= 0;
+    return SV_OK;
+}
+
 static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_noise_model *nm,
                           uint64_t seed, const double *params, size_t n_sets)
 {
@@ -906,7 +946,10 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     uint64_t gate_count;
     sv_status s = validate_and_expand(b, ops, n_ops, nm, rules, xo, ro01, ro10, gate_count);
     if (s != SV_OK) return s;
-    if (xo.empty()) return fail(SV_EINVAL, "empty circuit");
+    if (xo.empty()) {
+        if (!b->attached) return fail(SV_ESTATE, "no arena attached");
+        return run_empty(b);
+    }
 
     const int n = b->n;
     // terminal measurement: last op measures every qubit in order

@@ -102,6 +102,13 @@ def test_valid_circuit_needs_arena():
     assert e.value.status == 4  # SV_ESTATE
 
 
+def test_empty_circuit_is_valid_and_needs_arena():
+    # no ops is a valid circuit (every register 0); it still needs the arena
+    with pytest.raises(S.SvError) as e:
+        _run_unattached({"n_qubits": 3, "n_clbits": 3, "ops": []}, W.depol_model())
+    assert e.value.status == 4  # SV_ESTATE, not SV_EINVAL
+
+
 def test_results_before_run_are_refused():
     h = S.sv_batch_create(3, 4, S.SV_C64)
     try:

@@ -1,0 +1,166 @@
+"""Edge cases on the GPU, through the C ABI: empty and measurement-free
+circuits, one shot, shot counts that leave ragged waves, noise and readout
+that happen with probability 0 or 1, outcomes of probability 0, the
+resident / streamed size boundary and the largest state (30 qubits).
+Expected values are closed forms, or the FP64 oracle's per-shot registers."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import gpu_run, mismatches, oracle_memory, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(kind, qubits, params=None, clbits=None):
+    o = {"kind": kind, "qubits": list(qubits)}
+    if params is not None:
+        o["params"] = list(params)
+    if clbits is not None:
+        o["clbits"] = list(clbits)
+    return o
+
+
+def _measure_all(n):
+    return _op("measure", range(n), clbits=range(n))
+
+
+def _noise_full():
+    return W.noise_model(
+        [W.rule(["u3", "h", "x"], W.depolarizing_pauli(0.03, 1)),
+         W.rule(["u3", "h", "x"], W.amplitude_damping_kraus(0.04)),
+         W.rule(["cx", "cz"], W.depolarizing_pauli(0.06, 2))],
+        readout=(0.02, 0.03))
+
+
+@pytest.mark.parametrize("mode", ["batch", "branch", "plain"])
+@pytest.mark.parametrize("n", [3, 16])
+def test_empty_circuit(mode, n):
+    circ = {"n_qubits": n, "n_clbits": n, "ops": []}
+    shots = 37
+    say(f"case empty circuit n={n} {mode}")
+    dump = 0 if mode == "batch" else None
+    got = gpu_run(circ, _noise_full(), shots, dtype="c64", mode=mode, dump_shot=dump)
+    assert np.all(got["memory"] == 0)
+    assert got["counts"] == {0: shots}
+    if dump is not None:
+        st = got["state"]
+        assert st[0] == 1 and np.count_nonzero(st) == 1
+
+
+@pytest.mark.parametrize("n,tile", [(5, 0), (14, 12)])
+def test_circuit_without_measurement(n, tile):
+    circ = W.random_layered(n, 3, seed=4, measure_all=False)
+    opts = {"tile_qubits": tile} if tile else {}
+    say(f"case no measurement n={n}")
+    got = gpu_run(circ, _noise_full(), 50, dtype="c128", seed=2, **opts)
+    assert np.all(got["memory"] == 0)
+    assert got["counts"] == {0: 50}
+
+
+@pytest.mark.parametrize("mode", ["batch", "branch"])
+def test_single_shot_streamed(mode):
+    circ = W.random_layered(15, 4, seed=8, mid_measure=(2, (0, 3)))
+    noise = _noise_full()
+    say(f"case one shot n=15 {mode}")
+    got = gpu_run(circ, noise, 1, dtype="c128", mode=mode, seed=11, shot_offset=77)
+    exp = oracle_memory(circ, noise, 78, seed=11)[77:]
+    assert mismatches(got["memory"], exp) == 0
+
+
+@pytest.mark.parametrize("mode,shots,opts", [
+    ("batch", 23, {"workers": 7}),
+    ("batch", 513, {}),
+    ("branch", 37, {"workers": 5, "slots": 3}),
+])
+def test_ragged_shot_counts(mode, shots, opts):
+    circ = W.random_layered(14, 3, seed=6, mid_measure=(1, (2,)))
+    noise = _noise_full()
+    say(f"case ragged {mode} shots={shots} {opts}")
+    got = gpu_run(circ, noise, shots, dtype="c128", mode=mode, seed=5, **opts)
+    exp = oracle_memory(circ, noise, shots, seed=5)
+    assert mismatches(got["memory"], exp) == 0
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["batch", "branch"])
+@pytest.mark.parametrize("n", [5, 14])
+def test_certain_pauli_noise(n, mode, dtype):
+    # identity gates, each followed by an X with probability 1: every qubit
+    # ends in |1>, so every shot reads all ones
+    circ = {"n_qubits": n, "n_clbits": n,
+            "ops": [_op("u3", [q], (0.0, 0.0, 0.0)) for q in range(n)] + [_measure_all(n)]}
+    noise = W.noise_model([W.rule(["u3"], W.pauli_table([0, 1, 0, 0], ["I", "X", "Y", "Z"]))])
+    say(f"case certain X noise n={n} {mode} {dtype}")
+    got = gpu_run(circ, noise, 40, dtype=dtype, mode=mode, seed=1)
+    assert np.all(got["memory"] == (1 << n) - 1)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_certain_readout_flips(dtype):
+    # |q0 q2 = 1> measured, every recorded bit flipped: 0b0101 -> 0b1010
+    n = 4
+    circ = {"n_qubits": n, "n_clbits": n,
+            "ops": [_op("x", [0]), _op("x", [2]), _measure_all(n)]}
+    noise = W.noise_model([], readout=(1.0, 1.0))
+    say(f"case certain readout flips {dtype}")
+    got = gpu_run(circ, noise, 30, dtype=dtype, seed=3)
+    assert np.all(got["memory"] == 0b1010)
+
+
+@pytest.mark.parametrize("mode", ["batch", "branch"])
+@pytest.mark.parametrize("n,tile", [(3, 0), (15, 12)])
+def test_zero_probability_outcomes(n, tile, mode):
+    # measuring and resetting a qubit in |0> always reads 0, and the reset
+    # qubit reads 0 again; after X a qubit reads 1 with certainty
+    ops = []
+    for _ in range(3):
+        ops.append(_op("h", [1]))
+        ops.append(_op("h", [1]))  # with damping between, qubit 1 is left mixed
+        ops.append(_op("measure_reset", [0, 1], clbits=[n, n + 1]))
+    ops.append(_op("x", [n - 1]))
+    ops.append(_measure_all(n))
+    circ = {"n_qubits": n, "n_clbits": n + 2, "ops": ops}
+    noise = W.noise_model([W.rule(["h"], W.amplitude_damping_kraus(0.9))])
+    opts = {"tile_qubits": tile} if tile else {}
+    say(f"case zero-probability outcomes n={n} {mode}")
+    got = gpu_run(circ, noise, 60, dtype="c128", mode=mode, seed=9, **opts)
+    # qubit 1 after H, damping, H is random: compare with the oracle
+    exp = oracle_memory(circ, noise, 60, seed=9)
+    assert mismatches(got["memory"], exp) == 0
+    mem = got["memory"]
+    one = np.uint64(1)
+    # certain bits: the last qubit reads 1; qubit 0 (never touched) reads 0
+    # mid-circuit; qubits 0 and 1 were reset, so the final measure reads 0
+    assert np.all(((mem >> np.uint64(n - 1)) & one) == one)
+    assert np.all(((mem >> np.uint64(n)) & one) == 0)
+    assert np.all((mem & np.uint64(0b11)) == 0)
+
+
+@pytest.mark.parametrize("dtype,n", [("c64", 13), ("c64", 14), ("c128", 12), ("c128", 13)])
+def test_resident_streamed_boundary(dtype, n):
+    circ = W.random_layered(n, 4, seed=12, mid_measure=(2, (1,)))
+    noise = _noise_full()
+    shots = 200
+    say(f"case boundary {dtype} n={n}")
+    got = gpu_run(circ, noise, shots, dtype=dtype, seed=4)
+    exp = oracle_memory(circ, noise, shots, seed=4)
+    bad = mismatches(got["memory"], exp)
+    if dtype == "c128":
+        assert bad == 0
+    else:
+        assert bad <= 2
+    resident = got["stats"]["tile_qubits"] == n
+    assert resident == (n <= (13 if dtype == "c64" else 12))
+
+
+def test_largest_state_thirty_qubits():
+    # 8 GiB complex64 state: H on q0, X on q29, CX(29 -> 1), measure all
+    n = 30
+    circ = {"n_qubits": n, "n_clbits": n,
+            "ops": [_op("h", [0]), _op("x", [29]), _op("cx", [29, 1]), _measure_all(n)]}
+    say("case 30 qubits, c64, 8 shots")
+    got = gpu_run(circ, None, 8, dtype="c64", seed=2)
+    base = (1 << 29) | (1 << 1)
+    mem = got["memory"]
+    assert set(int(x) for x in mem) <= {base, base | 1}
