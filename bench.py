@@ -35,9 +35,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(dtype: str, shots_per_step: int):
+def measured_traffic(dtype: str, shots_per_step: int, mode: str):
     """HBM bytes per executor launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source, in the same mode
+    and with the same shots per launch."""
     path = os.path.join(ROOT, "profiles", f"exec_kernel_c3_20q_{dtype}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -45,7 +46,7 @@ def measured_traffic(dtype: str, shots_per_step: int):
         t = json.load(fh)
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
-    if int(t.get("shots_per_launch", -1)) != shots_per_step:
+    if int(t.get("shots_per_launch", -1)) != shots_per_step or t.get("mode", "batch") != mode:
         return None
     return float(t["hbm_bytes_per_launch"])
 
@@ -60,10 +61,11 @@ def cpu_baseline(circ, noise, gate_count: int, seed: int):
     return {"value": len(shots) * gate_count / dt, "unit": "shots*gates/s",
             "cores": cores, "kind": "oracle",
             "sample": f"shot ids 0..{len(shots) - 1} of the same workload "
-                      f"(one shot per core, {dt:.1f} s wall)"}
+                      f"(one shot per core, {dt:.1f} s wall)",
+            "full_job_estimate_s": round(100_000 * dt / len(shots), 1)}
 
 
-def other_form(circ, noise, seed, gates, shots, dtype, mode):
+def other_form(circ, noise, seed, gates, shots, dtype, mode, keep_memory=False):
     """One timed wave of the same workload in another precision or form
     (shot ids 0..shots-1), for the comparisons the metric names."""
     import torch
@@ -76,13 +78,76 @@ def other_form(circ, noise, seed, gates, shots, dtype, mode):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = sim.stats()
+    mem = sim.memory() if keep_memory else None
     sim.close()
+    torch.cuda.empty_cache()
     assert sum(counts.values()) == shots
-    return {"dtype": dtype, "mode": mode, "shots": shots,
-            "value": shots * gates / dt, "unit": "shots*gates/s",
-            "ms": round(dt * 1e3, 1),
-            "hbm_gbs": round(st["amp_bytes"] / (st["exec_ms"] * 1e-3) / 1e9, 1)
-            if st["exec_ms"] > 0 else None}
+    out = {"dtype": dtype, "mode": mode, "shots": shots,
+           "value": shots * gates / dt, "unit": "shots*gates/s",
+           "ms": round(dt * 1e3, 1),
+           "hbm_gbs": round(st["amp_bytes"] / (st["exec_ms"] * 1e-3) / 1e9, 1)
+           if st["exec_ms"] > 0 else None,
+           "passes_per_shot": round(st["passes"] / shots, 2)}
+    if mode == "branch":
+        out.update(slots=st["slots"], branches=st["branches"], restarts=st["restarts"])
+    return (out, mem) if keep_memory else out
+
+
+def shot_state(circ, noise, seed, dtype, shot):
+    """Normalised final state of one shot (complex128 copy)."""
+    from paper_2308_03399_amd import Simulator
+    sim = Simulator(circ["n_qubits"], 1, dtype=dtype, shot_offset=shot, dump_shot=0)
+    try:
+        sim.run(circ, noise, seed=seed)
+        return sim.state()
+    finally:
+        sim.close()
+
+
+def c64_vs_fp64(mem64, mem128, circ, noise, seed):
+    """Complex64 path against the FP64 path on the same shot ids: per-shot
+    agreement and total-variation distance of the counts (shared draws, so
+    the TVD is at most the disagreement rate), and for one shot the
+    amplitude error of its final state and the TVD of the output
+    distributions its final measurement samples from."""
+    import numpy as np
+    agree = float(np.mean(mem64 == mem128))
+    k64, c64 = np.unique(mem64, return_counts=True)
+    k128, c128 = np.unique(mem128, return_counts=True)
+    p = dict(zip(k64.tolist(), (c64 / c64.sum()).tolist()))
+    q = dict(zip(k128.tolist(), (c128 / c128.sum()).tolist()))
+    tvd = 0.5 * sum(abs(p.get(k, 0.0) - q.get(k, 0.0)) for k in set(p) | set(q))
+    a = shot_state(circ, noise, seed, "c64", 0)
+    b = shot_state(circ, noise, seed, "c128", 0)
+    fid = abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
+    pa, pb = np.abs(a) ** 2, np.abs(b) ** 2
+    return {"shots": int(mem64.size), "agreement": agree, "tvd": tvd,
+            "max_amp_err_shot0": float(np.max(np.abs(a - b))),
+            "infidelity_shot0": float(1.0 - fid),
+            # total-variation distance of the two output distributions the
+            # final measurement of shot 0 samples from
+            "output_tvd_shot0": float(0.5 * np.sum(np.abs(pa / pa.sum() - pb / pb.sum()))),
+            "reference": "complex128 GPU path on the same shot ids (per-shot equal to "
+                         "the FP64 oracle on sampled shots)"}
+
+
+def copy_ceiling_gbs(gib: int = 2, reps: int = 5) -> float:
+    """Device-to-device copy bandwidth (read + write bytes / time): the
+    attainable HBM rate beside the 8 TB/s peak."""
+    import torch
+    a = torch.empty(gib << 30, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (gib << 30) * reps / (ms * 1e-3) / 1e9
 
 
 def qft_comparison(n, shots=4000, p=0.01, plain_shots=40):
@@ -199,6 +264,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c128", action="store_true",
                     help="skip the complex128 wave reported beside the c64 value")
+    ap.add_argument("--no-branch", action="store_true",
+                    help="skip the shot-branching wave reported beside the batch value")
     ap.add_argument("--plain-shots", type=int, default=16,
                     help="shots of the plain per-shot FP64 form timed for the speedup (0: skip)")
     ap.add_argument("--qft", type=str, default="",
@@ -241,8 +308,11 @@ def main():
         counts = sim.counts(capacity=B)
         return sim.stats(), counts
 
+    mem_first = None  # per-shot registers of shot ids 0..B-1 (untimed warm-up)
     for i in range(args.warmup):
         step(i)
+        if i == 0:
+            mem_first = sim.memory()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -264,7 +334,7 @@ def main():
     alu_peak = FP32_VECTOR_PEAK_TF if args.dtype == "c64" else FP64_VECTOR_PEAK_TF
     frac_hbm = gbs / HBM_PEAK_GBS
     frac_alu = tfs / alu_peak
-    traffic = measured_traffic(args.dtype, B)
+    traffic = measured_traffic(args.dtype, B, args.mode)
     if frac_hbm >= frac_alu:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(frac_hbm, 4)}
@@ -309,8 +379,19 @@ def main():
         "roofline": roof,
     }
     sim.close()
+    copy_gbs = copy_ceiling_gbs()
+    roof["copy_ceiling_gbs"] = round(copy_gbs, 1)
+    roof["hbm_frac_of_copy"] = round(gbs / copy_gbs, 4)
     if not args.no_c128 and args.dtype == "c64":
-        out["c128"] = other_form(circ, noise, seed, gates, B, "c128", args.mode)
+        out["c128"], mem128 = other_form(circ, noise, seed, gates, B, "c128", args.mode,
+                                         keep_memory=True)
+        if mem_first is not None:
+            out["c64_vs_fp64"] = c64_vs_fp64(mem_first, mem128, circ, noise, seed)
+    if not args.no_branch and args.mode == "batch":
+        br = other_form(circ, noise, seed, gates, B, args.dtype, "branch")
+        br["note"] = ("shot-branching on the same shot ids: shots share a state until a "
+                      "draw splits them")
+        out["branch"] = br
     if args.plain_shots > 0:
         pl = other_form(circ, noise, seed, gates, args.plain_shots, "c128", "plain")
         pl["note"] = ("plain per-shot FP64 form: one state, one kernel per op, first "

@@ -163,7 +163,11 @@ sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
 
 /* Options (call before sv_batch_attach; some also between runs):
  *   "mode"         sv_mode                                   (default BATCH)
- *   "slots"        state slots in the arena; 0 = automatic
+ *   "slots"        state slots in the arena; 0 = automatic (batch mode: one
+ *                  per workgroup; branch mode: one per shot while they fit
+ *                  in half the device memory free at sizing time, and at
+ *                  least two per workgroup; fewer slots send shots to the
+ *                  waiting list)
  *   "workers"      persistent workgroups; 0 = automatic (fills the GPU)
  *   "tile_qubits"  qubits per LDS tile, 6..14; 0 = automatic
  *   "program_bytes" device bytes reserved for the op program (default 8 MiB)

@@ -88,6 +88,7 @@ struct sv_batch {
     int nbuf = 1;                      // LDS tile buffers of grouped streamed passes
     int cus = 0;
     int64_t wallclock_khz = 100000;
+    int64_t auto_slots = 0;            // branch mode's automatic slot count, fixed at first sizing
     // arena
     bool attached = false;
     char *arena = nullptr;
@@ -177,8 +178,17 @@ static sv_status derive(sv_batch *b)
                                                 : std::min<int64_t>(b->shots, 4 * (int64_t)b->workers))
                        : 0;
     } else if (b->mode == SV_MODE_BRANCH) {
-        b->slots = (int)(b->opt_slots > 0 ? b->opt_slots
-                                          : std::min<int64_t>(b->shots, 2 * (int64_t)b->workers));
+        // automatic: one slot per shot while they fit in half the free
+        // device memory (no waiting list), at least two per workgroup
+        // (decided once, so the footprint and the attach agree)
+        if (b->opt_slots <= 0 && b->auto_slots == 0) {
+            int64_t want = 2 * (int64_t)b->workers;
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+                want = std::max<int64_t>(want, (int64_t)(free_b / 2 / state_bytes(b)));
+            b->auto_slots = std::min<int64_t>({b->shots, want, (int64_t)1 << 24});
+        }
+        b->slots = (int)(b->opt_slots > 0 ? b->opt_slots : b->auto_slots);
         b->slots = std::max(b->slots, 1);
     } else {
         b->slots = b->workers;
@@ -814,6 +824,7 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
                         k == "program_bytes" || k == "dump_shot" || k == "engine" ||
                         k == "pipeline";
     if (sizing && b->attached) return fail(SV_ESTATE, "option %s must be set before attach", key);
+    if (sizing) b->auto_slots = 0;
     if (k == "mode") {
         if (v < 0 || v > 2) return fail(SV_EINVAL, "mode %lld", (long long)v);
         b->mode = (int)v;

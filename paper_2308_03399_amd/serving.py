@@ -153,6 +153,10 @@ class DeviceBackend:
         try:
             sv_batch_set_option(h, "mode", MODES[req.mode])
             sv_batch_set_option(h, "workers", workers)
+            if req.mode == "branch" and "slots" not in req.options:
+                # the library's automatic branch budget is half the free
+                # device memory; a shared device gets a per-chunk share
+                sv_batch_set_option(h, "slots", min(n_shots, 4 * workers))
             sv_batch_set_option(h, "shot_offset", offset)
             for k, v in req.options.items():
                 sv_batch_set_option(h, k, int(v))
