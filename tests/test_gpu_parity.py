@@ -331,6 +331,28 @@ def test_c3_full_size_sampled_shots():
     assert mismatches(np.asarray(got128["memory"])[ids128], exp128) == 0
 
 
+def test_c3_full_size_branch_mode():
+    # the benchmark's branch wave: 10,000 shots sharing states until their
+    # draws split them (one slot per shot). In complex64 it agrees with the
+    # batch wave within complex64 rounding (a shared state can be scaled
+    # differently before a reduction), and in complex128 it is the oracle's
+    w = W.workload("c3_20q")
+    shots = 10_000
+    say(f"case c3 branch mode, {shots} shots c64, against batch")
+    br = gpu_run(w["circuit"], w["noise"], shots, dtype="c64", mode="branch", seed=w["seed"])
+    ba = gpu_run(w["circuit"], w["noise"], shots, dtype="c64", seed=w["seed"])
+    st = br["stats"]
+    assert st["restarts"] == 0 and st["branches"] >= 1
+    agree = float(np.mean(br["memory"] == ba["memory"]))
+    say(f"branch/batch agreement {agree:.5f}, passes/shot {st['passes'] / shots:.2f}")
+    assert agree >= 0.995
+    say("case c3 branch mode c128, 256 shots")
+    got = gpu_run(w["circuit"], w["noise"], 256, dtype="c128", mode="branch", seed=w["seed"])
+    ids = list(range(4)) + list(range(252, 256))
+    exp = oracle.run(w["circuit"], w["noise"], ids, seed=w["seed"])
+    assert mismatches(np.asarray(got["memory"])[ids], exp) == 0
+
+
 # ---------------------------------------------------------------------------
 # Parameter sweeps: circuits differing only in U3 angles, one launch
 # ---------------------------------------------------------------------------
