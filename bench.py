@@ -21,6 +21,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+WORKLOADS = {
+    "c3_20q": {"steps": 10, "warmup": 1, "shots_per_step": 10_000, "plain_shots": 16,
+               "metric": "shots×gates/s and achieved HBM GB/s, 20q noisy 100k shots; c64 vs c128",
+               "describe": "c3_20q: 20 qubits x 60 layers random U3 + CX pairing; depolarizing "
+                           "1e-3 (1q) / 1e-2 (2q), amplitude damping 5e-3, readout 2%; "
+                           "100,000 shots as waves"},
+    "c4_26q": {"steps": 1, "warmup": 0, "shots_per_step": 2000, "plain_shots": 1,
+               "metric": "shots×gates/s and achieved HBM GB/s, 26q noisy 2000 shots",
+               "describe": "c4_26q: 26 qubits x 80 layers random U3 + CZ pairing; depolarizing "
+                           "1e-3 (1q) / 1e-2 (2q); 2000 shots in one launch"},
+}
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VECTOR_PEAK_TF = 157.3    # MI355X published FP32 vector
 FP64_VECTOR_PEAK_TF = 78.6
@@ -35,11 +46,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(dtype: str, shots_per_step: int, mode: str):
+def measured_traffic(workload: str, dtype: str, shots_per_step: int, mode: str):
     """HBM bytes per executor launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source, in the same mode
     and with the same shots per launch."""
-    path = os.path.join(ROOT, "profiles", f"exec_kernel_c3_20q_{dtype}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"exec_kernel_{workload}_{dtype}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -260,17 +271,20 @@ def serving_bench(n_requests: int, loads=(0.8,), max_active: int = 4):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3_20q", choices=sorted(WORKLOADS),
+                    help="c3_20q: the headline (default); c4_26q: 26 qubits x 80 layers U3+CZ, "
+                         "2000 shots in one launch")
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
     ap.add_argument("--mode", default="batch", choices=["batch", "branch"])
-    ap.add_argument("--shots-per-step", type=int, default=10_000)
+    ap.add_argument("--shots-per-step", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c128", action="store_true",
                     help="skip the complex128 wave reported beside the c64 value")
     ap.add_argument("--no-branch", action="store_true",
                     help="skip the shot-branching wave reported beside the batch value")
-    ap.add_argument("--plain-shots", type=int, default=16,
+    ap.add_argument("--plain-shots", type=int, default=None,
                     help="shots of the plain per-shot FP64 form timed for the speedup (0: skip)")
     ap.add_argument("--qft", type=str, default="",
                     help="instead of the headline workload: the paper's QFT comparison, "
@@ -281,6 +295,15 @@ def main():
     ap.add_argument("--serve-loads", type=str, default="0.8",
                     help="comma-separated offered loads, as fractions of the closed-loop capacity")
     args = ap.parse_args()
+    spec = WORKLOADS[args.workload]
+    for k in ("steps", "warmup", "shots_per_step", "plain_shots"):
+        if getattr(args, k) is None:
+            setattr(args, k, spec[k])
+    if args.workload != "c3_20q":
+        # 26-qubit states: no FP64 wave at full width (1 GiB per state), no
+        # branch wave (fewer slots than shots), no oracle timing (one shot
+        # is ~10 min of host time)
+        args.no_c128 = args.no_branch = args.no_cpu_baseline = True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: shots shard across GPUs by "
               "shot-id range with no exchange, which this build does not "
@@ -299,7 +322,7 @@ def main():
             qft_comparison(n)
         return
 
-    w = W.workload("c3_20q")
+    w = W.workload(args.workload)
     circ, noise, seed = w["circuit"], w["noise"], w["seed"]
     gates = W.count_gates(circ)
     B = args.shots_per_step
@@ -307,7 +330,7 @@ def main():
     stream = sim.stream
 
     def step(idx):
-        sim_opts_offset = (idx % max(1, (100_000 // B))) * B
+        sim_opts_offset = (idx % max(1, (w["shots"] // B))) * B
         from paper_2308_03399_amd import sv_batch_set_option
         sv_batch_set_option(sim.h, "shot_offset", sim_opts_offset)
         sim.run(circ, noise, seed=seed)
@@ -340,7 +363,7 @@ def main():
     alu_peak = FP32_VECTOR_PEAK_TF if args.dtype == "c64" else FP64_VECTOR_PEAK_TF
     frac_hbm = gbs / HBM_PEAK_GBS
     frac_alu = tfs / alu_peak
-    traffic = measured_traffic(args.dtype, B, args.mode)
+    traffic = measured_traffic(args.workload, args.dtype, B, args.mode)
     if frac_hbm >= frac_alu:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(frac_hbm, 4)}
@@ -358,7 +381,7 @@ def main():
     roof["alu_frac"] = round(frac_alu, 4)
 
     out = {
-        "metric": "shots×gates/s and achieved HBM GB/s, 20q noisy 100k shots; c64 vs c128",
+        "metric": spec["metric"],
         "value": value,
         "unit": "shots*gates/s",
         "n_gpus": 1,
@@ -371,9 +394,7 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {
-            "workload": "c3_20q: 20 qubits x 60 layers random U3 + CX pairing; "
-                        "depolarizing 1e-3 (1q) / 1e-2 (2q), amplitude damping 5e-3, "
-                        "readout 2%; 100,000 shots as waves",
+            "workload": spec["describe"],
             "shots_per_step": B,
             "total_shots": total_shots,
             "gates_per_shot": gates,
@@ -406,6 +427,8 @@ def main():
         out["plain_fp64"] = pl
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(circ, noise, gates, seed)
+    elif args.workload != "c3_20q":
+        out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
 
 

@@ -168,7 +168,9 @@ sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
  *                  in half the device memory free at sizing time, and at
  *                  least two per workgroup; fewer slots send shots to the
  *                  waiting list)
- *   "workers"      persistent workgroups; 0 = automatic (fills the GPU)
+ *   "workers"      persistent workgroups; 0 = automatic (fills the GPU; in
+ *                  batch mode, where each holds one state, at most as many
+ *                  states as fit in 80% of the device memory free at sizing)
  *   "tile_qubits"  qubits per LDS tile, 6..14; 0 = automatic
  *   "program_bytes" device bytes reserved for the op program (default 8 MiB)
  *   "dump_shot"    shot id whose state before the final op is kept for

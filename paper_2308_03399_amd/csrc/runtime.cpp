@@ -89,6 +89,7 @@ struct sv_batch {
     int cus = 0;
     int64_t wallclock_khz = 100000;
     int64_t auto_slots = 0;            // branch mode's automatic slot count, fixed at first sizing
+    int64_t auto_workers = 0;          // batch mode's memory-bounded worker count, same
     // arena
     bool attached = false;
     char *arena = nullptr;
@@ -170,6 +171,19 @@ static sv_status derive(sv_batch *b)
     if (per_cu < 1) return fail(SV_EDEVICE, "executor does not fit on a compute unit");
     int64_t w = b->opt_workers > 0 ? b->opt_workers : (int64_t)per_cu * b->cus;
     if (b->mode == SV_MODE_BATCH) w = std::min<int64_t>(w, b->shots);
+    // batch mode keeps one state per workgroup: the automatic count also
+    // stays within 80% of the free device memory (decided once, so the
+    // footprint and the attach agree)
+    if (b->mode == SV_MODE_BATCH && !b->resident && b->opt_workers <= 0) {
+        if (b->auto_workers == 0) {
+            int64_t cap = w;
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+                cap = (int64_t)((double)free_b * 0.8 / (double)state_bytes(b));
+            b->auto_workers = std::max<int64_t>(1, std::min<int64_t>(w, cap));
+        }
+        w = b->auto_workers;
+    }
     b->workers = (int)std::max<int64_t>(1, w);
     // state slots
     if (b->resident) {
@@ -824,7 +838,7 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
                         k == "program_bytes" || k == "dump_shot" || k == "engine" ||
                         k == "pipeline";
     if (sizing && b->attached) return fail(SV_ESTATE, "option %s must be set before attach", key);
-    if (sizing) b->auto_slots = 0;
+    if (sizing) b->auto_slots = b->auto_workers = 0;
     if (k == "mode") {
         if (v < 0 || v > 2) return fail(SV_EINVAL, "mode %lld", (long long)v);
         b->mode = (int)v;
@@ -1180,8 +1194,20 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
         st.workers = 1;
         st.slots = 1;
         st.tile_qubits = (uint32_t)n;
-        st.passes = (uint64_t)b->shots * xo.size();
-        st.amp_bytes = st.passes * 2 * state_bytes(b);
+        // state sweeps per shot: a gate reads and writes the state; a Kraus
+        // channel or a measurement adds a read-only reduction sweep; a Pauli
+        // channel moves data only when it draws a non-identity string
+        // (rare, not counted: the byte figure is a lower bound)
+        uint64_t rw = 0, ro = 0;
+        for (const XOp &x : xo) {
+            if (x.kind == -1 || x.kind == SV_OP_BFUNC) continue;
+            ++rw;
+            if (x.kind == -2 || x.kind == SV_OP_MEASURE || x.kind == SV_OP_RESET ||
+                x.kind == SV_OP_MEASURE_RESET)
+                ++ro;
+        }
+        st.passes = (uint64_t)b->shots * (rw + ro);
+        st.amp_bytes = (uint64_t)b->shots * (2 * rw + ro) * state_bytes(b);
         b->have_results = true;
         b->have_dump = false;
         return SV_OK;
