@@ -22,12 +22,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
+    "c1_10q": {"steps": 1, "warmup": 1, "shots_per_step": 1000, "plain_shots": 16, "dtype": "c128",
+               "metric": "shots×gates/s, 10q noisy 1000 shots (states resident in LDS)",
+               "describe": "c1_10q: 10 qubits x 20 layers random U3 + CX pairing; depolarizing "
+                           "1e-3 (1q) / 1e-2 (2q); 1000 shots in one launch"},
+    "c2_16q": {"steps": 1, "warmup": 1, "shots_per_step": 10_000, "plain_shots": 16,
+               "dtype": "c128",
+               "metric": "shots×gates/s and achieved HBM GB/s, 16q noisy 10k shots with "
+                         "mid-circuit measure and reset",
+               "describe": "c2_16q: 16 qubits x 40 layers random U3 + CX pairing; depolarizing "
+                           "1e-3 (1q) / 1e-2 (2q); measure and reset of qubits 0, 1 every 10 "
+                           "layers; 10,000 shots in one launch"},
     "c3_20q": {"steps": 10, "warmup": 1, "shots_per_step": 10_000, "plain_shots": 16,
+               "dtype": "c64",
                "metric": "shots×gates/s and achieved HBM GB/s, 20q noisy 100k shots; c64 vs c128",
                "describe": "c3_20q: 20 qubits x 60 layers random U3 + CX pairing; depolarizing "
                            "1e-3 (1q) / 1e-2 (2q), amplitude damping 5e-3, readout 2%; "
                            "100,000 shots as waves"},
     "c4_26q": {"steps": 1, "warmup": 0, "shots_per_step": 2000, "plain_shots": 1,
+               "dtype": "c64",
                "metric": "shots×gates/s and achieved HBM GB/s, 26q noisy 2000 shots",
                "describe": "c4_26q: 26 qubits x 80 layers random U3 + CZ pairing; depolarizing "
                            "1e-3 (1q) / 1e-2 (2q); 2000 shots in one launch"},
@@ -62,7 +75,7 @@ def measured_traffic(workload: str, dtype: str, shots_per_step: int, mode: str):
     return float(t["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(circ, noise, gate_count: int, seed: int):
+def cpu_baseline(circ, noise, gate_count: int, seed: int, job_shots: int):
     import oracle
     cores = len(os.sched_getaffinity(0))
     shots = list(range(cores))
@@ -73,7 +86,7 @@ def cpu_baseline(circ, noise, gate_count: int, seed: int):
             "cores": cores, "kind": "oracle",
             "sample": f"shot ids 0..{len(shots) - 1} of the same workload "
                       f"(one shot per core, {dt:.1f} s wall)",
-            "full_job_estimate_s": round(100_000 * dt / len(shots), 1)}
+            "full_job_estimate_s": round(job_shots * dt / len(shots), 1)}
 
 
 def other_form(circ, noise, seed, gates, shots, dtype, mode, keep_memory=False):
@@ -276,7 +289,7 @@ def main():
                          "2000 shots in one launch")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--dtype", default=None, choices=["c64", "c128"])
     ap.add_argument("--mode", default="batch", choices=["batch", "branch"])
     ap.add_argument("--shots-per-step", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -296,10 +309,10 @@ def main():
                     help="comma-separated offered loads, as fractions of the closed-loop capacity")
     args = ap.parse_args()
     spec = WORKLOADS[args.workload]
-    for k in ("steps", "warmup", "shots_per_step", "plain_shots"):
+    for k in ("steps", "warmup", "shots_per_step", "plain_shots", "dtype"):
         if getattr(args, k) is None:
             setattr(args, k, spec[k])
-    if args.workload != "c3_20q":
+    if args.workload == "c4_26q":
         # 26-qubit states: no FP64 wave at full width (1 GiB per state), no
         # branch wave (fewer slots than shots), no oracle timing (one shot
         # is ~10 min of host time)
@@ -426,8 +439,8 @@ def main():
         pl["speedup_of_value"] = round(value / pl["value"], 1)
         out["plain_fp64"] = pl
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(circ, noise, gates, seed)
-    elif args.workload != "c3_20q":
+        out["cpu_baseline"] = cpu_baseline(circ, noise, gates, seed, w["shots"])
+    elif args.workload == "c4_26q":
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
 
