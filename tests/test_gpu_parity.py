@@ -387,3 +387,27 @@ def test_parameter_sweep_matches_oracle_per_set(n, dtype, tile):
         exp = oracle.run(_with_angles(circ, params[s]), noise, ids, seed=8)
         bad += mismatches(np.asarray(mem)[ids], exp)
     assert bad == 0 if dtype == "c128" else bad <= 2
+
+
+@pytest.mark.parametrize("n,tile", [(6, 0), (14, 12)])
+def test_parameter_sweep_with_conditional_ops(n, tile):
+    # swept U3 angles together with conditional gates and branch ops: each
+    # set's shots are the oracle's shots of the circuit with that set's angles
+    circ = W.random_small(n, 60, seed=23, n_mid=3, p_cond=0.4)
+    noise = _noise_full(p1=0.03, p2=0.05, gamma=0.04)
+    n_u3 = sum(1 for op in circ["ops"] if op["kind"] == "u3")
+    assert n_u3 > 0 and any(op.get("cond") for op in circ["ops"])
+    n_sets, per = 3, 20
+    params = np.random.default_rng(9).uniform(0, 2 * math.pi, (n_sets, n_u3, 3))
+    say(f"case sweep with conditions n={n} tile={tile}")
+    opts = {"tile_qubits": tile} if tile else {}
+    sim = S.Simulator(n, n_sets * per, dtype="c128", spin_limit_ms=60000, **opts)
+    try:
+        sim.run_sweep(circ, noise, params, seed=4)
+        mem = sim.memory()
+    finally:
+        sim.close()
+    for s in range(n_sets):
+        ids = list(range(s * per, (s + 1) * per))
+        exp = oracle.run(_with_angles(circ, params[s]), noise, ids, seed=4)
+        assert mismatches(np.asarray(mem)[ids], exp) == 0
