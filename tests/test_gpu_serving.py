@@ -64,3 +64,20 @@ def test_poisson_replay_reports_latency():
     for r, res in zip(reqs, rep["results"]):
         assert res.memory.shape == (r.shots,)
         assert sum(res.counts.values()) == r.shots
+
+
+def test_large_request_chunked_at_default_capacity_equals_alone():
+    # a 20-qubit request split into chunks over the full device capacity,
+    # served beside small requests, gives the same registers as one launch
+    big = SV.Request(circuit=W.random_layered(20, 10, seed=300), noise=W.depol_model(),
+                     shots=2000, seed=77, id=100)
+    small = [SV.Request(circuit=W.random_layered(n, 6, seed=310 + n), noise=W.depol_model(),
+                        shots=300, seed=n, id=n) for n in (7, 11, 13)]
+    say("case serving: 20-qubit request chunked beside small ones")
+    with SV.Server(max_active=4, chunk_ms=40.0) as srv:
+        tickets = [srv.submit(big)] + [srv.submit(r) for r in small]
+        results = [t.wait(300) for t in tickets]
+    assert len(results[0].chunks) > 1
+    for r, res in zip([big] + small, results):
+        alone = gpu_run(r.circuit, r.noise, r.shots, dtype="c64", seed=r.seed)
+        assert mismatches(res.memory, alone["memory"]) == 0
