@@ -188,3 +188,39 @@ def test_device_wait_timeout_is_reported_and_the_handle_recovers():
     finally:
         sim.close()
     assert mismatches(mem, oracle_memory(circ, noise, shots, seed=3)) == 0
+
+
+@pytest.mark.parametrize("n,shots", [(6, 1000), (16, 3001)])
+def test_counts_histogram_contract(n, shots):
+    # sv_sample_counts: ascending keys with their counts, equal to the
+    # histogram of the per-shot registers; a too-small capacity returns
+    # SV_EINVAL with the required size written
+    import ctypes
+    import paper_2308_03399_amd as S
+    circ = W.random_layered(n, 3, seed=51)
+    noise = _noise_full()
+    say(f"case counts contract n={n} shots={shots}")
+    sim = S.Simulator(n, shots, dtype="c64")
+    try:
+        sim.run(circ, noise, seed=6)
+        mem = sim.memory()
+        keys, cnt = np.unique(mem, return_counts=True)
+        L = S.lib()
+        nu = ctypes.c_size_t(0)
+        # size query with no output arrays
+        st = L.sv_sample_counts(sim.h, None, None, 0, ctypes.byref(nu))
+        assert st == (1 if len(keys) > 0 else 0) and nu.value == len(keys)
+        # one slot short
+        k = np.zeros(len(keys), np.uint64)
+        c = np.zeros(len(keys), np.uint64)
+        nu.value = 0
+        st = L.sv_sample_counts(sim.h, k.ctypes.data, c.ctypes.data, len(keys) - 1,
+                                ctypes.byref(nu))
+        assert st == 1 and nu.value == len(keys)
+        # exact capacity
+        st = L.sv_sample_counts(sim.h, k.ctypes.data, c.ctypes.data, len(keys), ctypes.byref(nu))
+        assert st == 0 and nu.value == len(keys)
+    finally:
+        sim.close()
+    assert np.array_equal(k, keys) and np.array_equal(c, cnt.astype(np.uint64))
+    assert int(c.sum()) == shots
