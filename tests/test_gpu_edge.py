@@ -224,3 +224,19 @@ def test_counts_histogram_contract(n, shots):
         sim.close()
     assert np.array_equal(k, keys) and np.array_equal(c, cnt.astype(np.uint64))
     assert int(c.sum()) == shots
+
+
+@pytest.mark.parametrize("mode,n,tile", [("batch", 5, 0), ("batch", 14, 12), ("branch", 14, 12)])
+def test_random_keying_with_64_bit_seed_and_shot_ids(mode, n, tile):
+    # Philox counter (shot lo, shot hi, r, d) and key (seed lo, seed hi): a
+    # 64-bit seed and shot ids that cross 2^32 reach both high words
+    circ = W.random_layered(n, 3, seed=61, mid_measure=(1, (0,)))
+    noise = _noise_full()
+    seed = 0xDEADBEEFCAFEF00D
+    base = (1 << 32) - 5
+    shots = 10
+    opts = {"tile_qubits": tile} if tile else {}
+    say(f"case 64-bit keying {mode} n={n}")
+    got = gpu_run(circ, noise, shots, dtype="c128", mode=mode, seed=seed, shot_offset=base, **opts)
+    exp = oracle_memory(circ, noise, range(base, base + shots), seed=seed)
+    assert mismatches(got["memory"], exp) == 0
