@@ -75,21 +75,25 @@ def measured_traffic(workload: str, dtype: str, shots_per_step: int, mode: str):
     return float(t["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(circ, noise, gate_count: int, seed: int, job_shots: int):
+def cpu_baseline(circ, noise, gate_count: int, seed: int, job_shots: int, wave: int):
+    """The FP64 oracle timed on the host cores: one shot per core, ids
+    spread over the first wave (0..wave-1). Returns the baseline record and
+    the oracle's registers and decision margins for those ids."""
     import oracle
     cores = len(os.sched_getaffinity(0))
-    shots = list(range(cores))
+    shots = [k * (wave // cores) for k in range(cores)]
     t0 = time.perf_counter()
-    oracle.run(circ, noise, shots, seed=seed, n_threads=cores)
+    mem, marg = oracle.run(circ, noise, shots, seed=seed, n_threads=cores, want_margins=True)
     dt = time.perf_counter() - t0
-    return {"value": len(shots) * gate_count / dt, "unit": "shots*gates/s",
-            "cores": cores, "kind": "oracle",
-            "sample": f"shot ids 0..{len(shots) - 1} of the same workload "
-                      f"(one shot per core, {dt:.1f} s wall)",
-            "full_job_estimate_s": round(job_shots * dt / len(shots), 1)}
+    rec = {"value": len(shots) * gate_count / dt, "unit": "shots*gates/s",
+           "cores": cores, "kind": "oracle",
+           "sample": f"{len(shots)} shot ids spread over 0..{wave - 1} of the same workload "
+                     f"(one shot per core, {dt:.1f} s wall)",
+           "full_job_estimate_s": round(job_shots * dt / len(shots), 1)}
+    return rec, shots, mem, marg
 
 
-def other_form(circ, noise, seed, gates, shots, dtype, mode, keep_memory=False):
+def other_form(circ, noise, seed, gates, shots, dtype, mode, keep_memory=False, stats=False):
     """One timed wave of the same workload in another precision or form
     (shot ids 0..shots-1), for the comparisons the metric names."""
     import torch
@@ -114,6 +118,9 @@ def other_form(circ, noise, seed, gates, shots, dtype, mode, keep_memory=False):
            "passes_per_shot": round(st["passes"] / shots, 2)}
     if mode == "branch":
         out.update(slots=st["slots"], branches=st["branches"], restarts=st["restarts"])
+    out["near_ties"] = st["near_ties"]
+    if stats:
+        out["stats"] = st
     return (out, mem) if keep_memory else out
 
 
@@ -128,12 +135,31 @@ def shot_state(circ, noise, seed, dtype, shot):
         sim.close()
 
 
-def c64_vs_fp64(mem64, mem128, circ, noise, seed):
-    """Complex64 path against the FP64 path on the same shot ids: per-shot
-    agreement and total-variation distance of the counts (shared draws, so
-    the TVD is at most the disagreement rate), and for one shot the
-    amplitude error of its final state and the TVD of the output
-    distributions its final measurement samples from."""
+def wave_memory(circ, noise, seed, shots, dtype):
+    """Per-shot registers of shot ids 0..shots-1 (batch mode)."""
+    from paper_2308_03399_amd import Simulator
+    sim = Simulator(circ["n_qubits"], shots, dtype=dtype)
+    try:
+        sim.run(circ, noise, seed=seed)
+        return sim.memory()
+    finally:
+        sim.close()
+
+
+def c64_vs_fp64(mem64, mem128, circ, noise, seed, n_state_shots=64):
+    """Complex64 path against the FP64 path on the same shot ids.
+
+    * With the workload's readout error: per-shot agreement and the
+      total-variation distance of the two count histograms (shared draws,
+      so it is at most the disagreement rate).
+    * With readout error off (the register is then the sampled basis
+      index): each disagreement is split into a final sample that landed on
+      the neighbouring index (u*N between the complex64 and FP64 running
+      sums of one of the 2^n boundaries) and any other (a trajectory that
+      went another way at a Kraus choice).
+    * For n_state_shots shots spread over the wave: the TVD of the two
+      output distributions the final measurement samples from, the largest
+      amplitude error and the infidelity of the final states."""
     import numpy as np
     agree = float(np.mean(mem64 == mem128))
     k64, c64 = np.unique(mem64, return_counts=True)
@@ -141,18 +167,97 @@ def c64_vs_fp64(mem64, mem128, circ, noise, seed):
     p = dict(zip(k64.tolist(), (c64 / c64.sum()).tolist()))
     q = dict(zip(k128.tolist(), (c128 / c128.sum()).tolist()))
     tvd = 0.5 * sum(abs(p.get(k, 0.0) - q.get(k, 0.0)) for k in set(p) | set(q))
-    a = shot_state(circ, noise, seed, "c64", 0)
-    b = shot_state(circ, noise, seed, "c128", 0)
-    fid = abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
-    pa, pb = np.abs(a) ** 2, np.abs(b) ** 2
-    return {"shots": int(mem64.size), "agreement": agree, "tvd": tvd,
-            "max_amp_err_shot0": float(np.max(np.abs(a - b))),
-            "infidelity_shot0": float(1.0 - fid),
-            # total-variation distance of the two output distributions the
-            # final measurement of shot 0 samples from
-            "output_tvd_shot0": float(0.5 * np.sum(np.abs(pa / pa.sum() - pb / pb.sum()))),
+    B = int(mem64.size)
+    noise0 = dict(noise, readout=[0.0, 0.0])
+    a = wave_memory(circ, noise0, seed, B, "c64")
+    b = wave_memory(circ, noise0, seed, B, "c128")
+    diff = np.nonzero(a != b)[0]
+    gap = np.abs(a[diff].astype(np.int64) - b[diff].astype(np.int64))
+    adjacent = int(np.sum(gap == 1))
+    tvds, errs, infid = [], [], []
+    for k in range(n_state_shots):
+        shot = k * (B // n_state_shots)
+        sa = shot_state(circ, noise, seed, "c64", shot)
+        sb = shot_state(circ, noise, seed, "c128", shot)
+        pa, pb = np.abs(sa) ** 2, np.abs(sb) ** 2
+        tvds.append(0.5 * float(np.sum(np.abs(pa / pa.sum() - pb / pb.sum()))))
+        errs.append(float(np.max(np.abs(sa - sb))))
+        fid = abs(np.vdot(sa, sb)) ** 2 / (np.vdot(sa, sa).real * np.vdot(sb, sb).real)
+        infid.append(float(1.0 - fid))
+    return {"shots": B, "agreement": agree, "tvd": tvd,
+            "readout_off": {"disagreements": int(diff.size),
+                            "adjacent_index": adjacent,
+                            "other": int(diff.size) - adjacent,
+                            "other_rate": (int(diff.size) - adjacent) / B},
+            "final_states": {"shots": n_state_shots,
+                             "output_tvd_mean": float(np.mean(tvds)),
+                             "output_tvd_max": float(np.max(tvds)),
+                             "max_amp_err": float(np.max(errs)),
+                             "infidelity_max": float(np.max(infid))},
             "reference": "complex128 GPU path on the same shot ids (per-shot equal to "
                          "the FP64 oracle on sampled shots)"}
+
+
+def one_launch(args):
+    """One sv_run_circuit (+ counts) of a workload for a profiler: prints
+    the library's stats as one JSON line."""
+    import workloads as W
+    from paper_2308_03399_amd import Simulator
+    w = W.workload(args.workload)
+    dtype = args.dtype or w["dtype"]
+    opts = {"tile_qubits": args.tile_qubits} if args.tile_qubits else {}
+    sim = Simulator(w["circuit"]["n_qubits"], args.one_launch, dtype=dtype, mode=args.mode, **opts)
+    sim.run(w["circuit"], w["noise"], seed=w["seed"])
+    sim.counts()
+    st = sim.stats()
+    st.update({"workload": args.workload, "shots": args.one_launch, "dtype": dtype,
+               "mode": args.mode})
+    sim.close()
+    print(json.dumps(st), flush=True)
+
+
+def copy_calibrate(mib: int, reps: int = 3):
+    """A plain device copy of a known size (torch's copy kernel), whose
+    FETCH_SIZE / WRITE_SIZE counter readings scale those counters to bytes."""
+    import torch
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {mib} MiB x {reps}", flush=True)
+
+
+def error_ratio_sweep(qubits, probs, shots=4000, plain_shots=16):
+    """The paper's error-ratio experiment (Sec. V-D): QFT with depolarizing
+    noise of rate p after every gate, as a Pauli channel or as the
+    equivalent Kraus list, 4000 shots; batched (batch mode) and branched
+    forms in complex64 against the plain per-shot FP64 form (timed on its
+    first shot ids; linear in shots). One JSON line per point."""
+    import workloads as W
+    for n in qubits:
+        circ = W.qft(n)
+        gates = W.count_gates(circ)
+        for form in ("pauli", "kraus"):
+            for p in probs:
+                noise = W.qft_noise(p, form)
+                other_form(circ, noise, 0, gates, min(shots, 256), "c64", "batch")  # warm-up
+                ba = other_form(circ, noise, 0, gates, shots, "c64", "batch", stats=True)
+                br = other_form(circ, noise, 0, gates, shots, "c64", "branch", stats=True)
+                pl = other_form(circ, noise, 0, gates, plain_shots, "c128", "plain")
+                plain_ms = pl["ms"] / plain_shots * shots
+                line = {"experiment": "error_ratio", "workload": f"qft_{n}q", "noise": form,
+                        "p": p, "shots": shots, "gates_per_shot": gates,
+                        "batch_c64_ms": ba["ms"], "batch_passes_per_shot": ba["passes_per_shot"],
+                        "batch_reductions_per_shot": round(ba["stats"]["reductions"] / shots, 3),
+                        "branch_c64_ms": br["ms"], "branch_states": br["branches"] + 1,
+                        "branch_passes_per_shot": br["passes_per_shot"],
+                        "plain_fp64_ms": round(plain_ms, 1),
+                        "batch_speedup_over_plain": round(plain_ms / ba["ms"], 1),
+                        "branch_speedup_over_plain": round(plain_ms / br["ms"], 1)}
+                print(json.dumps(line), flush=True)
 
 
 def copy_ceiling_gbs(gib: int = 2, reps: int = 5) -> float:
@@ -175,7 +280,7 @@ def copy_ceiling_gbs(gib: int = 2, reps: int = 5) -> float:
 
 
 def qft_comparison(n, shots=4000, p=0.01, plain_shots=40):
-    """The paper's single-GPU experiment (Sec. V-A): QFT with 1% Pauli or
+    """The paper's single-GPU experiment (Sec. V-B): QFT with 1% Pauli or
     Kraus noise, 4000 shots, the batched and branched forms against the
     plain per-shot form (timed on its first shot ids; linear in shots)."""
     import workloads as W
@@ -307,8 +412,19 @@ def main():
                          "requests (closed loop, then Poisson at --serve-loads x its capacity)")
     ap.add_argument("--serve-loads", type=str, default="0.8",
                     help="comma-separated offered loads, as fractions of the closed-loop capacity")
+    ap.add_argument("--error-sweep", type=str, default="",
+                    help="instead of the headline workload: the paper's error-ratio experiment "
+                         "(QFT, 4000 shots), comma-separated qubit counts")
+    ap.add_argument("--error-probs", type=str, default="1e-4,1e-3,1e-2,5e-2")
+    ap.add_argument("--one-launch", type=int, default=0,
+                    help="for profilers: one sv_run_circuit of this many shots of --workload, "
+                         "its stats as one JSON line")
+    ap.add_argument("--tile-qubits", type=int, default=0)
+    ap.add_argument("--copy-calibrate", type=int, default=0,
+                    help="for counter calibration: a device copy of this many MiB, 3 times")
     args = ap.parse_args()
     spec = WORKLOADS[args.workload]
+    args.dtype_given = args.dtype
     for k in ("steps", "warmup", "shots_per_step", "plain_shots", "dtype"):
         if getattr(args, k) is None:
             setattr(args, k, spec[k])
@@ -327,6 +443,17 @@ def main():
     import workloads as W
     from paper_2308_03399_amd import Simulator
 
+    if args.copy_calibrate:
+        copy_calibrate(args.copy_calibrate)
+        return
+    if args.one_launch:
+        args.dtype = getattr(args, "dtype_given", None)
+        one_launch(args)
+        return
+    if args.error_sweep:
+        error_ratio_sweep([int(x) for x in args.error_sweep.split(",")],
+                          [float(x) for x in args.error_probs.split(",")])
+        return
     if args.serve:
         serving_bench(args.serve, tuple(float(x) for x in args.serve_loads.split(",")))
         return
@@ -422,11 +549,14 @@ def main():
     copy_gbs = copy_ceiling_gbs()
     roof["copy_ceiling_gbs"] = round(copy_gbs, 1)
     roof["hbm_frac_of_copy"] = round(gbs / copy_gbs, 4)
+    mem128 = None
     if not args.no_c128 and args.dtype == "c64":
         out["c128"], mem128 = other_form(circ, noise, seed, gates, B, "c128", args.mode,
                                          keep_memory=True)
         if mem_first is not None:
             out["c64_vs_fp64"] = c64_vs_fp64(mem_first, mem128, circ, noise, seed)
+    elif args.dtype == "c128":
+        mem128 = mem_first
     if not args.no_branch and args.mode == "batch":
         br = other_form(circ, noise, seed, gates, B, args.dtype, "branch")
         br["note"] = ("shot-branching on the same shot ids: shots share a state until a "
@@ -439,7 +569,16 @@ def main():
         pl["speedup_of_value"] = round(value / pl["value"], 1)
         out["plain_fp64"] = pl
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(circ, noise, gates, seed, w["shots"])
+        import numpy as np
+        rec, ids, omem, omarg = cpu_baseline(circ, noise, gates, seed, w["shots"], B)
+        out["cpu_baseline"] = rec
+        if mem128 is not None:
+            # the oracle's registers against the FP64 GPU path on the same ids
+            got = np.asarray(mem128)[ids]
+            out["oracle_mismatches"] = int(np.sum(got != omem))
+            out["oracle_check"] = {"shot_ids": ids, "oracle_min_margin": float(np.min(omarg)),
+                                   "oracle_near_ties": int(np.sum(omarg < 1e-9)),
+                                   "fp64_wave_near_ties": out.get("c128", {}).get("near_ties")}
     elif args.workload == "c4_26q":
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

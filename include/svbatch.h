@@ -57,7 +57,9 @@ typedef enum {
 typedef enum {
     SV_MODE_BATCH = 0,    /* every shot owns a state (Sec. IV-A)          */
     SV_MODE_BRANCH = 1,   /* shots share states until split (Sec. IV-B)   */
-    SV_MODE_PLAIN = 2     /* one state, one kernel per op, host decisions */
+    SV_MODE_PLAIN = 2     /* one state, one kernel per op, device
+                             decisions: the conventional per-shot form
+                             of Sec. III-C                               */
 } sv_mode;
 
 /* Op kinds of sv_op.kind. Gates act on q[0..nq-1]; for CX q[0] is the
@@ -154,10 +156,17 @@ typedef struct {
     uint32_t tile_buffers;     /* LDS tile buffers of streamed grouped passes (1|2) */
     uint64_t groups;           /* register groups executed per sweep, summed       */
     uint64_t uops;             /* register micro-ops executed per sweep, summed    */
+    uint64_t near_ties;        /* state-dependent decisions (Kraus, measure, final
+                                  sample) whose relative margin is below 1e-9:
+                                  see sv_get_margins                               */
 } sv_stats;
 
 /* Create a handle for n_qubits (1..30) and n_shots (>= 1) in the given
- * storage dtype. No device work. SV_EINVAL on bad sizes. */
+ * storage dtype: the per-shot state vectors of 2^n_qubits amplitudes that
+ * the batched execution of Sec. IV-A keeps for all shots (Sec. IV-A, data
+ * structure), complex64 or complex128. No device work; the handle owns no
+ * device memory until sv_batch_attach. SV_EINVAL on bad sizes or dtype;
+ * *out is NULL on failure. */
 sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
                           sv_batch **out);
 
@@ -175,7 +184,15 @@ sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
  *   "program_bytes" device bytes reserved for the op program (default 8 MiB)
  *   "dump_shot"    shot id whose state before the final op is kept for
  *                  sv_get_state; -1 disables (default)
- *   "spin_limit_ms" device wait bound of the work queue (default 300000)
+ *   "spin_limit_ms" progress watchdog of the work queue (default 300000): a
+ *                  workgroup waiting for a record gives up, and the run
+ *                  fails with SV_EDEVICE, once this long has passed with no
+ *                  workgroup completing a sweep or a record. A wait may
+ *                  last as long as other workgroups keep progressing (a
+ *                  long unsplit record, the tail of a run)
+ *   "spin_elapsed" 1: the bound above counts from the start of each wait,
+ *                  whatever the other workgroups do (forces the failure
+ *                  path from the host in tests); 0 (default): watchdog
  *   "shot_offset"  global id of shot 0 (default 0): shot i of the handle draws
  *                  the randoms of global shot shot_offset + i, so a large job
  *                  can run as consecutive waves, or be split across devices,
@@ -198,7 +215,11 @@ sv_status sv_batch_attach(sv_batch *b, void *device_arena, uint64_t arena_bytes,
                           void *hip_stream);
 
 /* Run all shots of the circuit ops[0..n_ops-1] under the noise model nm
- * (NULL: noiseless) with Philox seed `seed`. Validates first (qubits < n and
+ * (NULL: noiseless) with Philox seed `seed`: the multi-shot noise
+ * simulation of Sec. III-B (a circuit, a noise model and a shot count in,
+ * one classical register per shot out), executed as batched shots
+ * (Sec. IV-A), shot-branching (Sec. IV-B) or the plain per-shot form
+ * (Sec. III-C) according to the "mode" option. Validates first (qubits < n and
  * distinct within an op, clbits < 64, probabilities, Kraus completeness):
  * SV_EINVAL without touching the device. Blocks until the device work of
  * the run has finished. On any failure the handle is left in a state where
@@ -232,6 +253,21 @@ sv_status sv_sample_counts(sv_batch *b, uint64_t *keys, uint64_t *counts,
 /* Per-shot classical registers of the last run ("memory"), shot order;
  * n must equal the shot count. */
 sv_status sv_get_memory(sv_batch *b, uint64_t *creg_per_shot, size_t n);
+
+/* Per-shot decision margins of the last run, shot order; n must equal the
+ * shot count. A Kraus or measure choice compares u*N with the running sums
+ * C_0 <= C_1 <= ... of its candidates (Sec. III-B Kraus pseudo-code,
+ * Sec. IV-A measure pseudo-code; the final measurement samples the same way
+ * over all 2^n outcomes). Its margin is the distance from u*N to the
+ * boundaries that separate the chosen candidate j from its neighbours
+ * (C_{j-1} if j > 0, C_j if j is not the last candidate), divided by N; a
+ * choice made by the rounding fall-back has margin 0. out[s] is the
+ * smallest margin of shot s, +inf if it made no such choice. Choices that
+ * need no state (Pauli draws, readout flips, Kraus draws below the smallest
+ * eigenvalue of K_0^dagger K_0) compare with host constants and are not
+ * counted. Two exact implementations can disagree on a shot only where its
+ * margin is of the order of their rounding error. */
+sv_status sv_get_margins(sv_batch *b, double *margins, size_t n);
 
 /* State of shot "dump_shot" before the last op of the circuit (normalised,
  * interleaved re/im doubles, 2^n complex). SV_ESTATE if none was kept. */

@@ -58,7 +58,7 @@ def lib():
             ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P, P, ctypes.c_int,
             P, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
             ctypes.c_uint64, ctypes.c_long, P, P, ctypes.c_int, P,
-            ctypes.c_int]
+            ctypes.c_int, P]
         L.oracle_uniform.restype = ctypes.c_double
         L.oracle_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64,
                                      ctypes.c_uint32, ctypes.c_uint32]
@@ -163,12 +163,16 @@ def _pack(circuit: Dict, noise: Optional[Dict]):
 
 def run(circuit: Dict, noise: Optional[Dict], shots, seed: int = 0,
         n_threads: Optional[int] = None, stop_at: int = -1,
-        want_state: bool = False):
+        want_state: bool = False, want_margins: bool = False):
     """Per-shot classical registers ("memory") for the given shot ids.
 
     ``shots``: an int (ids 0..shots-1) or an iterable of shot ids.
     With ``want_state`` only the first id is simulated and its state after
     ``stop_at`` expanded ops (all if negative) is returned as well.
+    With ``want_margins`` the smallest relative decision margin of each shot
+    (``traj.c`` header: distance of u*N to the nearest running-sum boundary
+    of its Kraus and measure choices, over N; +inf without such a choice) is
+    returned after the memory.
     """
     if isinstance(shots, (int, np.integer)):
         ids = np.arange(int(shots), dtype=np.int64)
@@ -182,6 +186,7 @@ def run(circuit: Dict, noise: Optional[Dict], shots, seed: int = 0,
     state = np.zeros(2 << n, dtype=np.float64) if want_state else None
     if n_threads is None:
         n_threads = len(os.sched_getaffinity(0))
+    margins = np.zeros(max(len(ids), 1), dtype=np.float64)
     n_x = lib().oracle_run(
         n, len(circuit["ops"]), a["kind"].ctypes.data, a["nq"].ctypes.data,
         a["q"].ctypes.data, a["c"].ctypes.data, a["par"].ctypes.data,
@@ -190,13 +195,17 @@ def run(circuit: Dict, noise: Optional[Dict], shots, seed: int = 0,
         a["rnt"].ctypes.data, a["roff"].ctypes.data, a["probs"].ctypes.data,
         a["codes"].ctypes.data, a["kmats"].ctypes.data, a["ro01"], a["ro10"],
         int(seed), len(ids), ids.ctypes.data, mem.ctypes.data, int(stop_at),
-        state.ctypes.data if want_state else None, int(n_threads))
+        state.ctypes.data if want_state else None, int(n_threads),
+        margins.ctypes.data)
     if n_x < 0:
         raise ValueError("oracle rejected the circuit")
     mem = mem[:len(ids)]
+    out = [mem]
     if want_state:
-        return mem, state.view(np.complex128)
-    return mem
+        out.append(state.view(np.complex128))
+    if want_margins:
+        out.append(margins[:len(ids)])
+    return out[0] if len(out) == 1 else tuple(out)
 
 
 def counts(memory: Iterable[int]) -> Dict[int, int]:

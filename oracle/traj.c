@@ -36,6 +36,14 @@
  *    skipped op keeps its place in the op numbering (its draws are unused).
  *  - Readout error (named in Sec. III-B, no model given): each recorded bit
  *    flips independently, 0->1 with p01 and 1->0 with p10, from its own draw.
+ *  - Decision margin (not an arithmetic step: a record of how close each
+ *    state-dependent choice came to going the other way). For a Kraus or
+ *    measure decision with running sums C_0 <= C_1 <= ... over n_c
+ *    candidates, x = u*N and chosen index j, the margin is the distance
+ *    from x to the nearest boundary that separates j from a neighbour:
+ *    C_{j-1} if j > 0 and C_j if j < n_c - 1, divided by N; a choice made
+ *    by the rounding fall-back has margin 0. Each shot reports the smallest
+ *    margin of its decisions (+inf if it made none).
  *  - Random numbers: u = U(seed, shot, r, d) from Philox4x32-10 (Salmon,
  *    Moraes, Dror, Shaw, SC'11) with key = (seed lo, seed hi) and counter
  *    = (shot lo, shot hi, r, d); r is the op's index in the expanded list,
@@ -242,6 +250,23 @@ static void scale(cplx *psi, int n, double f)
     for (uint64_t i = 0; i < dim; ++i) psi[i] *= f;
 }
 
+/* Relative decision margin (see the header): prev = C_{j-1} (unused when
+ * j == 0), cur = C_j (unused when j is the last candidate). */
+static double decision_margin(double x, double N, int j, int n_cand, double prev,
+                              double cur, int fell_back)
+{
+    if (fell_back) return 0.0;
+    double m = INFINITY;
+    if (j > 0 && x - prev < m) m = x - prev;
+    if (j < n_cand - 1 && cur - x < m) m = cur - x;
+    return N > 0 ? m / N : 0.0;
+}
+
+static void note_margin(double *mmin, double m)
+{
+    if (mmin && m < *mmin) *mmin = m;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Noise channels                                                            */
 /* ------------------------------------------------------------------------ */
@@ -272,12 +297,12 @@ static void pauli_channel(cplx *psi, int n, const xop *op, const xrule *ru,
  * order, accumulate p_j = ||K_j psi||^2 and take the first j whose running
  * sum exceeds u*N; psi <- K_j psi / sqrt(p_j). Returns the chosen j. */
 static int kraus_channel(cplx *psi, cplx *work, int n, const xop *op,
-                         const xrule *ru, double u)
+                         const xrule *ru, double u, double *mmin)
 {
     uint64_t dim = 1ull << n;
     int k = ru->nq, sub = 1 << k;
     double N = norm2(psi, n);
-    double run = 0.0;
+    double run = 0.0, prev = 0.0;
     int chosen = -1, last_nonzero = -1;
     double p_chosen = 0.0;
     for (int j = 0; j < ru->n_terms; ++j) {
@@ -286,9 +311,12 @@ static int kraus_channel(cplx *psi, cplx *work, int n, const xop *op,
         apply_dense(work, n, k, op->q, m);
         double p = norm2(work, n);
         if (p > 0) last_nonzero = j;
+        prev = run;
         run += p;
         if (u * N < run) { chosen = j; p_chosen = p; break; }
     }
+    note_margin(mmin, decision_margin(u * N, N, chosen < 0 ? last_nonzero : chosen,
+                                      ru->n_terms, prev, run, chosen < 0));
     if (chosen < 0) {
         chosen = last_nonzero;
         const cplx *m = (const cplx *)(ru->mats + (size_t)chosen * sub * sub * 2);
@@ -303,7 +331,7 @@ static int kraus_channel(cplx *psi, cplx *work, int n, const xop *op,
 
 /* Measure (and reset) of qubits op->q[0..nq-1] (Sec. IV-A, measure/reset
  * pseudo-code). Returns the outcome pattern. */
-static uint64_t measure(cplx *psi, int n, const xop *op, double u)
+static uint64_t measure(cplx *psi, int n, const xop *op, double u, double *mmin)
 {
     uint64_t dim = 1ull << n;
     int m = op->nq;
@@ -316,13 +344,17 @@ static uint64_t measure(cplx *psi, int n, const xop *op, double u)
     }
     double N = 0.0;
     for (uint64_t o = 0; o < n_out; ++o) N += P[o];
-    double run = 0.0;
+    double run = 0.0, prev = 0.0;
     int64_t chosen = -1, last_nonzero = -1;
     for (uint64_t o = 0; o < n_out; ++o) {
         if (P[o] > 0) last_nonzero = (int64_t)o;
+        prev = run;
         run += P[o];
         if (u * N < run) { chosen = (int64_t)o; break; }
     }
+    note_margin(mmin, decision_margin(u * N, N, (int)(chosen < 0 ? last_nonzero : chosen),
+                                      n_out > 0x7fffffff ? 0x7fffffff : (int)n_out,
+                                      prev, run, chosen < 0));
     if (chosen < 0) chosen = last_nonzero;
     double f = 1.0 / sqrt(P[chosen]);
     for (uint64_t i = 0; i < dim; ++i) {
@@ -381,7 +413,8 @@ static int expand(int n_ops, const xop *ops, int n_rules, const xrule *rules,
 /* ------------------------------------------------------------------------ */
 static uint64_t run_shot(int n, int n_x, const xop *x, const xrule *rules,
                          double ro01, double ro10, uint64_t seed,
-                         uint64_t shot, int stop_at, cplx *psi, cplx *work)
+                         uint64_t shot, int stop_at, cplx *psi, cplx *work,
+                         double *mmin)
 {
     uint64_t dim = 1ull << n;
     memset(psi, 0, dim * sizeof(cplx));
@@ -407,13 +440,13 @@ static uint64_t run_shot(int n, int n_x, const xop *x, const xrule *rules,
             break;
         case O_KRAUS_CH:
             kraus_channel(psi, work, n, op, &rules[op->rule],
-                          oracle_uniform(seed, shot, (uint32_t)r, 0));
+                          oracle_uniform(seed, shot, (uint32_t)r, 0), mmin);
             break;
         case O_MEASURE:
         case O_MEASURE_RESET:
         case O_RESET: {
             uint64_t o = measure(psi, n, op,
-                                 oracle_uniform(seed, shot, (uint32_t)r, 0));
+                                 oracle_uniform(seed, shot, (uint32_t)r, 0), mmin);
             if (op->kind != O_RESET) {
                 for (int t = 0; t < op->nq; ++t) {
                     uint64_t bit = (o >> t) & 1ull;
@@ -446,6 +479,8 @@ static uint64_t run_shot(int n, int n_x, const xop *x, const xrule *rules,
 /* Pauli, into kmats (doubles) for Kraus).                                  */
 /* shots[n_sel] -> memory[n_sel]. If state_out != NULL, the state of        */
 /* shots[0] after the first stop_at expanded ops (all if < 0) is written.   */
+/* If margin_out != NULL, margin_out[s] receives the smallest decision      */
+/* margin of shot s (see the header).                                       */
 /* Returns the expanded op count, or -1 on an input error.                  */
 /* ------------------------------------------------------------------------ */
 int oracle_run(int n, int n_ops, const int *kind, const int *nq,
@@ -457,7 +492,7 @@ int oracle_run(int n, int n_ops, const int *kind, const int *nq,
                const int *codes, const double *kmats, double ro01,
                double ro10, uint64_t seed, long n_sel, const int64_t *shots,
                uint64_t *memory, int stop_at, double *state_out,
-               int n_threads)
+               int n_threads, double *margin_out)
 {
     if (n < 1 || n > 30 || n_ops < 0) return -1;
     xop *ops = (xop *)calloc((size_t)n_ops + 1, sizeof(xop));
@@ -505,8 +540,10 @@ int oracle_run(int n, int n_ops, const int *kind, const int *nq,
     if (state_out && n_sel > 0) {
         cplx *psi = (cplx *)malloc(dim * sizeof(cplx));
         cplx *work = (cplx *)malloc(dim * sizeof(cplx));
+        double mm = INFINITY;
         memory[0] = run_shot(n, n_x, x, rules, ro01, ro10, seed,
-                             (uint64_t)shots[0], stop_at, psi, work);
+                             (uint64_t)shots[0], stop_at, psi, work, &mm);
+        if (margin_out) margin_out[0] = mm;
         memcpy(state_out, psi, dim * sizeof(cplx));
         free(psi);
         free(work);
@@ -516,9 +553,12 @@ int oracle_run(int n, int n_ops, const int *kind, const int *nq,
             cplx *psi = (cplx *)malloc(dim * sizeof(cplx));
             cplx *work = (cplx *)malloc(dim * sizeof(cplx));
 #pragma omp for schedule(dynamic, 1)
-            for (long s = 0; s < n_sel; ++s)
+            for (long s = 0; s < n_sel; ++s) {
+                double mm = INFINITY;
                 memory[s] = run_shot(n, n_x, x, rules, ro01, ro10, seed,
-                                     (uint64_t)shots[s], stop_at, psi, work);
+                                     (uint64_t)shots[s], stop_at, psi, work, &mm);
+                if (margin_out) margin_out[s] = mm;
+            }
             free(psi);
             free(work);
         }

@@ -31,7 +31,7 @@ MAX_INLINE = 8
 
 EXPORTED = ["sv_batch_create", "sv_batch_footprint", "sv_batch_attach",
             "sv_batch_set_option", "sv_run_circuit", "sv_run_sweep", "sv_sample_counts",
-            "sv_get_memory", "sv_get_state", "sv_get_stats",
+            "sv_get_memory", "sv_get_margins", "sv_get_state", "sv_get_stats",
             "sv_batch_destroy", "sv_last_error"]
 
 
@@ -86,7 +86,7 @@ class sv_stats(ctypes.Structure):
                 ("static_passes", ctypes.c_uint32), ("flops", ctypes.c_uint64),
                 ("exec_ms", ctypes.c_double), ("exec_launches", ctypes.c_uint32),
                 ("tile_buffers", ctypes.c_uint32), ("groups", ctypes.c_uint64),
-                ("uops", ctypes.c_uint64)]
+                ("uops", ctypes.c_uint64), ("near_ties", ctypes.c_uint64)]
 
     def as_dict(self) -> Dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -121,6 +121,7 @@ def lib() -> ctypes.CDLL:
     L.sv_sample_counts.argtypes = [P, P, P, ctypes.c_size_t,
                                    ctypes.POINTER(ctypes.c_size_t)]
     L.sv_get_memory.argtypes = [P, P, ctypes.c_size_t]
+    L.sv_get_margins.argtypes = [P, P, ctypes.c_size_t]
     L.sv_get_state.argtypes = [P, P, ctypes.c_size_t]
     L.sv_get_stats.argtypes = [P, ctypes.POINTER(sv_stats)]
     L.sv_batch_destroy.argtypes = [P]
@@ -195,6 +196,12 @@ def sv_sample_counts(h: int, capacity: int = 0) -> Dict[int, int]:
 def sv_get_memory(h: int, n_shots: int) -> np.ndarray:
     out = np.zeros(n_shots, dtype=np.uint64)
     _check(lib().sv_get_memory(h, out.ctypes.data, n_shots))
+    return out
+
+
+def sv_get_margins(h: int, n_shots: int) -> np.ndarray:
+    out = np.zeros(n_shots, dtype=np.float64)
+    _check(lib().sv_get_margins(h, out.ctypes.data, n_shots))
     return out
 
 
@@ -328,6 +335,9 @@ class Simulator:
 
     def memory(self) -> np.ndarray:
         return sv_get_memory(self.h, self.n_shots)
+
+    def margins(self) -> np.ndarray:
+        return sv_get_margins(self.h, self.n_shots)
 
     def state(self) -> np.ndarray:
         return sv_get_state(self.h, self.n_qubits)

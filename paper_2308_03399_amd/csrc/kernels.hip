@@ -127,6 +127,12 @@ __device__ __forceinline__ void st_rel(uint32_t *p, uint32_t v)
 
 template <class R> struct Mat2 { R r[4], i[4]; };
 
+// Pauli term code of a drawn term: x | z << 8 | ny << 16 (0: identity).
+__device__ __forceinline__ uint32_t pauli_code(const ExecParams &P, const DevRule &ru, int d)
+{
+    return (uint32_t)P.pool[ru.codes + (uint32_t)d];
+}
+
 template <class R>
 __device__ __forceinline__ Mat2<R> load_m2(const double *m, double s)
 {
@@ -215,6 +221,7 @@ struct WgShared {
     double tsum_n;
     int term_tile;
     int split_cond;  // STOP_SPLIT: the stopping op's condition differs between shots
+    int n_distinct;  // terms drawn in a record split by term rank
     int n_ug;
     uint64_t pass_flops;
     unsigned long long st[ST_COUNT];
@@ -356,40 +363,68 @@ __device__ void sweep_mat1(Ctx<R> &c, uint32_t b, const Mat2<R> &m, bool diag)
     __syncthreads();
 }
 
-// 4x4 matrix, row-major interleaved re/im in doubles, index bit t <-> b[t].
-template <class R>
-__device__ void sweep_mat2(Ctx<R> &c, uint32_t b0, uint32_t b1, const double *m,
-                           double s)
+// Dense 2^NQ x 2^NQ matrix m (row-major, interleaved re/im doubles, times
+// s) on tile bits b[0..NQ-1]; bit t of its row/column index <-> b[t]. Each
+// thread owns the 2^NQ amplitudes of one base index: it holds them in
+// registers and writes every output row straight back to its own slot.
+template <class R, int NQ>
+__device__ void sweep_dense_t(Ctx<R> &c, const uint8_t *b, const double *m, double s)
 {
     using A = typename V2<R>::T;
-    R mr[16], mi[16];
+    constexpr int D = 1 << NQ;
+    uint32_t bits[NQ], sorted[NQ];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        mr[e] = (R)(m[2 * e] * s);
-        mi[e] = (R)(m[2 * e + 1] * s);
-    }
-    const uint32_t lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
-    const uint32_t quarter = c.tsize >> 2;
-    const uint32_t m0 = 1u << b0, m1 = 1u << b1;
+    for (int t = 0; t < NQ; ++t) bits[t] = sorted[t] = b[t];
+    // ascending bit positions for the zero insertion
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+#pragma unroll
+        for (int j = 0; j + 1 < NQ - i; ++j)
+            if (sorted[j] > sorted[j + 1]) {
+                const uint32_t t = sorted[j];
+                sorted[j] = sorted[j + 1];
+                sorted[j + 1] = t;
+            }
     lds<A> *L = c.L;
-    for (uint32_t p = c.tid; p < quarter; p += kWG) {
-        const uint32_t base = ins0(ins0(p, lo), hi);
-        const uint32_t idx[4] = {base, base | m0, base | m1, base | m0 | m1};
-        A v[4], o[4];
+    const uint32_t nbase = c.tsize >> NQ;
+    for (uint32_t p = c.tid; p < nbase; p += kWG) {
+        uint32_t base = p;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) v[a] = L[c.at(idx[a])];
+        for (int t = 0; t < NQ; ++t) base = ins0(base, sorted[t]);
+        A v[D];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            A acc = cmul<A, R>(mr[4 * a], mi[4 * a], v[0]);
+        for (int a = 0; a < D; ++a) {
+            uint32_t idx = base;
 #pragma unroll
-            for (int bb = 1; bb < 4; ++bb)
-                acc = cmac<A, R>(acc, mr[4 * a + bb], mi[4 * a + bb], v[bb]);
-            o[a] = acc;
+            for (int t = 0; t < NQ; ++t) idx |= ((uint32_t)(a >> t) & 1u) << bits[t];
+            v[a] = L[c.at(idx)];
         }
+        for (int a = 0; a < D; ++a) {
+            A acc;
+            acc.x = 0;
+            acc.y = 0;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) L[c.at(idx[a])] = o[a];
+            for (int bb = 0; bb < D; ++bb)
+                acc = cmac<A, R>(acc, (R)(m[2 * (a * D + bb)] * s), (R)(m[2 * (a * D + bb) + 1] * s), v[bb]);
+            uint32_t idx = base;
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) idx |= ((uint32_t)(a >> t) & 1u) << bits[t];
+            L[c.at(idx)] = acc;
+        }
     }
     __syncthreads();
+}
+
+template <class R>
+__device__ __noinline__ void sweep_dense(Ctx<R> &c, int nq, const uint8_t *b, const double *m,
+                                         double s)
+{
+    switch (nq) {
+    case 2: sweep_dense_t<R, 2>(c, b, m, s); break;
+    case 3: sweep_dense_t<R, 3>(c, b, m, s); break;
+    case 4: sweep_dense_t<R, 4>(c, b, m, s); break;
+    default: sweep_dense_t<R, 5>(c, b, m, s); break;
+    }
 }
 
 template <class R>
@@ -518,21 +553,21 @@ __device__ __noinline__ void apply_op(Ctx<R> &c, const DevOp &op, int d, double 
         sweep_mat1(c, op.lb[0], m, (op.flags & DF_DIAG) != 0);
         break;
     }
-    case DK_MAT2:
-        sweep_mat2(c, op.lb[0], op.lb[1], P.pool + op.mat, 1.0);
+    case DK_MATK:
+        sweep_dense(c, op.nq, op.lb, P.pool + op.mat, 1.0);
         break;
     case DK_CX: sweep_cx(c, op.lb[0], op.lb[1]); break;
     case DK_CZ: sweep_cz(c, op.lb[0], op.lb[1]); break;
     case DK_SWAP: sweep_swap(c, op.lb[0], op.lb[1]); break;
     case DK_PAULI: {
-        const DevRule &ru = P.rules[op.rule];
-        if ((ru.ident_mask >> d) & 1u) break;
+        const uint32_t code = pauli_code(P, P.rules[op.rule], d);
+        if (code == 0) break;  // identity
         uint32_t xl = 0, zl = 0;
         for (int t = 0; t < op.nq; ++t) {
-            xl |= ((ru.xcode[d] >> t) & 1u) << op.lb[t];
-            zl |= ((ru.zcode[d] >> t) & 1u) << op.lb[t];
+            xl |= ((code >> t) & 1u) << op.lb[t];
+            zl |= ((code >> (8 + t)) & 1u) << op.lb[t];
         }
-        sweep_pauli(c, xl, zl, ru.ny[d]);
+        sweep_pauli(c, xl, zl, code >> 16);
         break;
     }
     case DK_KRAUS: {
@@ -545,7 +580,7 @@ __device__ __noinline__ void apply_op(Ctx<R> &c, const DevOp &op, int d, double 
             const bool diag = m[2] == 0.0 && m[3] == 0.0 && m[4] == 0.0 && m[5] == 0.0;
             sweep_mat1(c, op.lb[0], mm, diag);
         } else {
-            sweep_mat2(c, op.lb[0], op.lb[1], m, s);
+            sweep_dense(c, (int)ru.nq, op.lb, m, s);
         }
         break;
     }
@@ -560,8 +595,8 @@ __device__ __forceinline__ uint64_t op_flops(const ExecParams &P, const DevOp &o
 {
     switch (op.kind) {
     case DK_MAT1: return flops_mat1((op.flags & DF_DIAG) != 0);
-    case DK_MAT2: return 30;
-    case DK_KRAUS: return P.rules[op.rule].nq == 1 ? 14 : 30;
+    case DK_MATK: return 8ull * (1ull << op.nq) - 2;
+    case DK_KRAUS: return 8ull * (1ull << P.rules[op.rule].nq) - 2;
     case DK_MEASURE: return 2;
     default: return 0;
     }
@@ -1001,10 +1036,10 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
                 break;
             }
             case DK_PAULI: {
-                const DevRule &ru = P.rules[op.rule];
-                if ((ru.ident_mask >> d) & 1u) break;
+                const uint32_t code = pauli_code(P, P.rules[op.rule], d);
+                if (code == 0) break;  // identity
                 for (int t = 0; t < op.nq; ++t) {
-                    const uint32_t x = (ru.xcode[d] >> t) & 1u, z = (ru.zcode[d] >> t) & 1u;
+                    const uint32_t x = (code >> t) & 1u, z = (code >> (8 + t)) & 1u;
                     if (!x && !z) continue;
                     // X = [[0,1],[1,0]], Z = [[1,0],[0,-1]], Y = [[0,-i],[i,0]]
                     double pm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1049,6 +1084,59 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
 }
 
 // ----------------------------------------------------------- reductions
+// Squared norm and ||K_j v||^2 of a Kraus channel on NQ >= 2 tile bits
+// b[0..NQ-1] (nm matrices of 2^NQ x 2^NQ FP64 complex at K), in FP64.
+template <class R, int NQ>
+__device__ void reduce_kraus_dense(Ctx<R> &c, const uint8_t *b, const double *K, int nm,
+                                   double (&acc)[kMaxRed])
+{
+    constexpr int D = 1 << NQ;
+    uint32_t bits[NQ], sorted[NQ];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) bits[t] = sorted[t] = b[t];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+#pragma unroll
+        for (int j = 0; j + 1 < NQ - i; ++j)
+            if (sorted[j] > sorted[j + 1]) {
+                const uint32_t t = sorted[j];
+                sorted[j] = sorted[j + 1];
+                sorted[j + 1] = t;
+            }
+    const uint32_t nbase = c.tsize >> NQ;
+    for (uint32_t p = c.tid; p < nbase; p += kWG) {
+        uint32_t base = p;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) base = ins0(base, sorted[t]);
+        double vr[D], vi[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            uint32_t idx = base;
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) idx |= ((uint32_t)(a >> t) & 1u) << bits[t];
+            const auto v = c.L[c.at(idx)];
+            vr[a] = v.x;
+            vi[a] = v.y;
+            acc[0] += fma(vr[a], vr[a], vi[a] * vi[a]);
+        }
+        for (int j = 0; j < nm && j < kMaxKraus; ++j) {
+            const double *m = K + (size_t)j * D * D * 2;
+            double sj = 0;
+            for (int a = 0; a < D; ++a) {
+                double wr = 0, wi = 0;
+#pragma unroll
+                for (int bb = 0; bb < D; ++bb) {
+                    const double mr = m[2 * (a * D + bb)], mi = m[2 * (a * D + bb) + 1];
+                    wr += mr * vr[bb] - mi * vi[bb];
+                    wi += mr * vi[bb] + mi * vr[bb];
+                }
+                sj += fma(wr, wr, wi * wi);
+            }
+            acc[1 + j] += sj;
+        }
+    }
+}
+
 // Accumulate, over the tile, the squared norm and the candidate weights of
 // op `op` (Kraus: ||K_j v||^2; measure: outcome probabilities).
 template <class R>
@@ -1080,36 +1168,11 @@ __device__ __noinline__ void reduce_tile(Ctx<R> &c, const DevOp &op, double (&ac
                 }
             }
         } else {
-            const uint32_t b0 = op.lb[0], b1 = op.lb[1];
-            const uint32_t lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
-            const uint32_t quarter = c.tsize >> 2;
-            for (uint32_t p = c.tid; p < quarter; p += kWG) {
-                const uint32_t base = ins0(ins0(p, lo), hi);
-                const uint32_t idx[4] = {base, base | (1u << b0), base | (1u << b1),
-                                         base | (1u << b0) | (1u << b1)};
-                double vr[4], vi[4];
-                for (int a = 0; a < 4; ++a) {
-                    const A v = L[c.at(idx[a])];
-                    vr[a] = v.x;
-                    vi[a] = v.y;
-                    acc[0] += fma(vr[a], vr[a], vi[a] * vi[a]);
-                }
-#pragma unroll
-                for (int j = 0; j < kMaxKraus; ++j) {
-                    if (j >= nm) break;
-                    const double *m = K + j * 32;
-                    double s = 0;
-                    for (int a = 0; a < 4; ++a) {
-                        double wr = 0, wi = 0;
-                        for (int bb = 0; bb < 4; ++bb) {
-                            const double mr = m[2 * (4 * a + bb)], mi = m[2 * (4 * a + bb) + 1];
-                            wr += mr * vr[bb] - mi * vi[bb];
-                            wi += mr * vi[bb] + mi * vr[bb];
-                        }
-                        s += fma(wr, wr, wi * wi);
-                    }
-                    acc[1 + j] += s;
-                }
+            switch (ru.nq) {
+            case 2: reduce_kraus_dense<R, 2>(c, op.lb, K, nm, acc); break;
+            case 3: reduce_kraus_dense<R, 3>(c, op.lb, K, nm, acc); break;
+            case 4: reduce_kraus_dense<R, 4>(c, op.lb, K, nm, acc); break;
+            default: reduce_kraus_dense<R, 5>(c, op.lb, K, nm, acc); break;
             }
         }
     } else {  // DK_MEASURE
@@ -1330,19 +1393,46 @@ __device__ __forceinline__ int pauli_pick(const ExecParams &P, const DevRule &ru
     return (int)ru.n_terms - 1;
 }
 
-// First candidate whose running sum of S.red[1..] exceeds u*N; if rounding
-// leaves none, the last candidate with a non-zero weight.
-__device__ __forceinline__ int red_pick(const lds<WgShared> &S, int cnt, double u)
+// Relative decision margin: distance from x to the running-sum boundaries
+// that separate the chosen candidate j from its neighbours (prev = C_{j-1}
+// if j > 0, cur = C_j if j is not the last candidate), over N. A choice made
+// by the rounding fall-back has margin 0.
+__device__ __forceinline__ double rel_margin(double x, double N, int j, int cnt, double prev,
+                                             double cur, bool fell_back)
 {
-    const double x = u * S.red[0];
-    double run = 0;
+    if (fell_back || !(N > 0)) return 0.0;
+    double m = __builtin_inf();
+    if (j > 0) m = fmin(m, x - prev);
+    if (j < cnt - 1) m = fmin(m, cur - x);
+    return m / N;
+}
+
+// First candidate whose running sum of S.red[1..] exceeds u*N; if rounding
+// leaves none, the last candidate with a non-zero weight. N is the squared
+// norm of the same sweep: for a Kraus channel its own sum (S.red[0]), for a
+// measurement the sum of the outcome probabilities in outcome order.
+__device__ __forceinline__ int red_pick(const lds<WgShared> &S, int cnt, double u,
+                                        bool norm_from_outcomes, double &margin)
+{
+    double N = S.red[0];
+    if (norm_from_outcomes) {
+        N = 0;
+        for (int o = 0; o < cnt; ++o) N += S.red[1 + o];
+    }
+    const double x = u * N;
+    double run = 0, prev = 0;
     int last = -1;
     for (int o = 0; o < cnt; ++o) {
         const double p = S.red[1 + o];
         if (p > 0) last = o;
+        prev = run;
         run += p;
-        if (x < run) return o;
+        if (x < run) {
+            margin = rel_margin(x, N, o, cnt, prev, run, false);
+            return o;
+        }
     }
+    margin = 0.0;
     return last < 0 ? 0 : last;
 }
 
@@ -1376,13 +1466,27 @@ __device__ __noinline__ void record_bits(const ExecParams &P, const DevOp &op, u
     creg_store(P.memory + shot, m);
 }
 
-// Outcome of shot `shot` at random op `op` (after its reduction, if any).
+// Outcome of shot `shot` at random op `op` (after its reduction, if any),
+// with the relative margin of a state-dependent choice (+inf for a Pauli
+// draw, whose thresholds are host constants).
 __device__ __forceinline__ int outcome_of(const ExecParams &P, const lds<WgShared> &S,
-                                          const DevOp &op, uint64_t shot)
+                                          const DevOp &op, uint64_t shot, double &margin)
 {
     const double u = philox_u01(P.seed, P.shot_base + shot, op.r, 0);
+    margin = __builtin_inf();
     if (op.kind == DK_PAULI) return pauli_pick(P, P.rules[op.rule], u);
-    return red_pick(S, red_count(P, op), u);
+    return red_pick(S, red_count(P, op), u, op.kind == DK_MEASURE, margin);
+}
+
+// Keep the smallest decision margin of a shot (device-scope accesses: the
+// shot's record may have been run by other workgroups before). Returns 1
+// for a near-tie.
+__device__ __forceinline__ int note_margin(const ExecParams &P, uint64_t shot, double m)
+{
+    if (!(m < __builtin_inf())) return 0;
+    const uint64_t bits = __builtin_bit_cast(uint64_t, m);
+    if (bits < creg_load(P.margins + shot)) creg_store(P.margins + shot, bits);
+    return m < kNearTie ? 1 : 0;
 }
 
 // Value of a condition (or branch-op predicate) for one shot.
@@ -1453,12 +1557,50 @@ __device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j, boo
     const int m = S.hi - S.lo;
     const int chunk = (m + kWG - 1) / kWG;
     const int my_lo = S.lo + min(m, tid * chunk), my_hi = S.lo + min(m, (tid + 1) * chunk);
+    // Shots are grouped into 16 buckets. The bucket of an outcome is the
+    // outcome itself, except for a Pauli channel of more than 16 terms:
+    // there it is the rank of the drawn term among the terms drawn in this
+    // record, and when more than 16 distinct terms are drawn, ranks from
+    // 15 on share bucket 15, whose shots are left undecided and split
+    // again by their own record (at least 15 terms are settled per split)
+    // (bitmap of the drawn terms and its prefix counts in the pass's
+    // decision area, unused between the sweep and the next plan)
+    const bool ranked = !cnd && op.kind == DK_PAULI && P.rules[op.rule].n_terms > 16;
+    constexpr int kW = kMaxPauliTerms / 32;
+    static_assert(2 * kW * 4 <= kMaxPassOps * 2, "term bitmap fits the decision area");
+    lds<uint32_t> *obits = (lds<uint32_t> *)c.dec;
+    lds<int> *obase = (lds<int> *)(obits + kW);
+    if (ranked) {
+        for (int w = tid; w < kW; w += kWG) obits[w] = 0;
+        __syncthreads();
+        for (int i = my_lo; i < my_hi; ++i) {
+            double mg;
+            const int o = outcome_of(P, S, op, (uint64_t)P.shot_perm[i], mg);
+            atomicOr((uint32_t *)&obits[o >> 5], 1u << (o & 31));
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int run = 0;
+            for (int w = 0; w < kW; ++w) {
+                obase[w] = run;
+                run += __popc(obits[w]);
+            }
+            S.n_distinct = run;
+        }
+        __syncthreads();
+    }
+    auto bucket_of = [&](int o) -> int {
+        if (!ranked) return o;
+        const int r = obase[o >> 5] + __popc(obits[o >> 5] & ((1u << (o & 31)) - 1u));
+        return r < 15 ? r : 15;
+    };
     int my_cnt[16];
 #pragma unroll
     for (int o = 0; o < 16; ++o) my_cnt[o] = 0;
     for (int i = my_lo; i < my_hi; ++i) {
         const uint64_t sh = (uint64_t)P.shot_perm[i];
-        const int o = cnd ? cond_of(P, op, sh) : outcome_of(P, S, op, sh);
+        double mg;
+        const int o = bucket_of(cnd ? cond_of(P, op, sh) : outcome_of(P, S, op, sh, mg));
 #pragma unroll
         for (int q = 0; q < 16; ++q) my_cnt[q] += (o == q);
     }
@@ -1479,7 +1621,23 @@ __device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j, boo
         int off = S.lo, g = 0;
         for (int o = 0; o < 16; ++o) {
             if (S.tot[o] == 0) continue;
-            S.grp_o[g] = o;
+            int val = o;  // the outcome of bucket o (-1: undecided)
+            if (ranked) {
+                val = -1;
+                if (o < 15 || S.n_distinct <= 16) {
+                    int seen = 0;
+                    for (int w = 0; w < kW && val < 0; ++w) {
+                        const uint32_t bw = obits[w];
+                        if (seen + __popc(bw) > o) {
+                            uint32_t x = bw;
+                            for (int k = seen; k < o; ++k) x &= x - 1u;  // drop lower set bits
+                            val = w * 32 + __builtin_ctz(x);
+                        }
+                        seen += __popc(bw);
+                    }
+                }
+            }
+            S.grp_o[g] = val;
             S.grp_lo[g] = off;
             S.grp_hi[g] = off + S.tot[o];
             off += S.tot[o];
@@ -1504,24 +1662,31 @@ __device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j, boo
     }
     // scatter into shot_tmp, then copy back
     {
+        // groups are in bucket order: group g holds the g-th non-empty bucket
         int pos[16];
-        for (int o = 0; o < 16; ++o) {
-            int base = 0;
-            for (int g = 0; g < S.n_groups; ++g)
-                if (S.grp_o[g] == o) base = S.grp_lo[g];
-            pos[o] = base + c.cnt[o * kWG + tid];
+        {
+            int g = 0;
+            for (int o = 0; o < 16; ++o) {
+                const int base = S.tot[o] ? S.grp_lo[g++] : 0;
+                pos[o] = base + c.cnt[o * kWG + tid];
+            }
         }
+        int ties = 0;
         for (int i = my_lo; i < my_hi; ++i) {
             const int shot = P.shot_perm[i];
-            const int o = cnd ? cond_of(P, op, (uint64_t)shot) : outcome_of(P, S, op, (uint64_t)shot);
+            double mg = __builtin_inf();
+            const int o = cnd ? cond_of(P, op, (uint64_t)shot) : outcome_of(P, S, op, (uint64_t)shot, mg);
+            if (!cnd) ties += note_margin(P, (uint64_t)shot, mg);
+            const int bk = bucket_of(o);
             int p = 0;
 #pragma unroll
             for (int q = 0; q < 16; ++q)
-                if (o == q) p = pos[q]++;
+                if (bk == q) p = pos[q]++;
             P.shot_tmp[p] = shot;
             if (!cnd && op.kind == DK_MEASURE && (op.flags & DF_RECORD))
                 record_bits(P, op, (uint64_t)shot, (uint32_t)o);
         }
+        if (ties) atomicAdd((unsigned long long *)&S.st[ST_NEARTIES], (unsigned long long)ties);
     }
     __threadfence_block();
     __syncthreads();
@@ -1872,7 +2037,10 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
             if (c.tid == 0) S.fresh = 0;
         }
     }
-    if (c.tid == 0) S.st[ST_FLOPS] += flops * (uint64_t)c.tsize;
+    if (c.tid == 0) {
+        S.st[ST_FLOPS] += flops * (uint64_t)c.tsize;
+        __hip_atomic_fetch_add(&P.ctl->heartbeat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (want_reduce) {
         wg_reduce(c, acc, 1 + red_count(P, rop));
         if (c.tid == 0) S.st[ST_REDUCTIONS] += 1;
@@ -1893,7 +2061,9 @@ __device__ __noinline__ void decide(Ctx<R> &c)
     if (m == 1) {
         if (c.tid == 0) {
             const uint64_t shot = (uint64_t)P.shot_perm[S.lo];
-            const int o = outcome_of(P, S, op, shot);
+            double mg;
+            const int o = outcome_of(P, S, op, shot, mg);
+            S.st[ST_NEARTIES] += note_margin(P, shot, mg);
             if (op.kind == DK_MEASURE && (op.flags & DF_RECORD)) record_bits(P, op, shot, (uint32_t)o);
             S.cursor = j;
             S.pending = o;
@@ -2046,6 +2216,7 @@ __device__ __noinline__ void terminal_sample(Ctx<R> &c)
             tile_prefix();
         }
         const double excl = t ? tsums[t - 1] : 0.0;
+        int ties = 0;
         for (int i = S.lo + tid; i < S.hi; i += kWG) {
             if (P.shot_tmp[i] != (int)t) continue;
             const uint64_t shot = (uint64_t)P.shot_perm[i];
@@ -2056,6 +2227,20 @@ __device__ __noinline__ void terminal_sample(Ctx<R> &c)
                 if (x < excl + D[mid]) hi = mid; else lo = mid + 1;
             }
             uint32_t e = lo;
+            // margin: the tile boundaries that chose tile t, then the
+            // in-tile boundaries that chose entry e (the last entry of the
+            // state has no upper boundary)
+            double mg = 0.0;
+            if (e < c.tsize && x < tsums[t]) {
+                const bool last_tile = t + 1 == c.n_tiles;
+                mg = __builtin_inf();
+                if (t > 0) mg = fmin(mg, x - excl);
+                if (!last_tile) mg = fmin(mg, tsums[t] - x);
+                if (e > 0) mg = fmin(mg, x - (excl + D[e - 1]));
+                if (!(last_tile && e == c.tsize - 1)) mg = fmin(mg, excl + D[e] - x);
+                mg = N > 0 ? mg / N : 0.0;
+            }
+            ties += note_margin(P, shot, mg);
             if (e >= c.tsize) {  // rounding: last non-zero entry of the tile
                 e = c.tsize - 1;
                 while (e > 0 && !(D[e] > D[e - 1])) --e;
@@ -2070,6 +2255,7 @@ __device__ __noinline__ void terminal_sample(Ctx<R> &c)
             }
             creg_store(P.memory + shot, mm);
         }
+        if (ties) atomicAdd((unsigned long long *)&S.st[ST_NEARTIES], (unsigned long long)ties);
         __syncthreads();
     }
 }
@@ -2182,7 +2368,12 @@ exec_kernel(ExecParams P)
             if (ld_rlx(&ctl->error) == 0) {
                 const uint32_t t = atomicAdd(&ctl->q_head, 1u);
                 if (t < (uint32_t)P.queue_cap && (P.branch_mode || t < ctl->n_initial)) {
-                    const unsigned long long t0 = wall_clock64();
+                    // progress watchdog: the wait may last as long as other
+                    // workgroups keep completing sweeps (a long unsplit
+                    // record, the tail of the run); it fails only after
+                    // spin_limit ticks in which no workgroup progressed
+                    unsigned long long t0 = wall_clock64();
+                    uint32_t hb = ld_rlx(&ctl->heartbeat);
                     for (;;) {
                         // poll relaxed; one acquire fence once the record is published
                         if (ld_rlx(&P.ready[t])) {
@@ -2200,7 +2391,11 @@ exec_kernel(ExecParams P)
                             break;
                         }
                         if (ld_rlx_i(&ctl->outstanding) <= 0) break;
-                        if (spin_expired(t0, P.spin_limit)) {
+                        const uint32_t hb2 = ld_rlx(&ctl->heartbeat);
+                        if (hb2 != hb && !P.spin_elapsed) {
+                            hb = hb2;
+                            t0 = wall_clock64();
+                        } else if (spin_expired(t0, P.spin_limit)) {
                             atomicOr(&ctl->error, kErrTimeout);
                             break;
                         }
@@ -2289,6 +2484,7 @@ exec_kernel(ExecParams P)
         if (tid == 0) {
             if (!P.resident && !P.private_slots && S.slot >= 0) slot_push(P, S.slot);
             __threadfence();
+            __hip_atomic_fetch_add(&P.ctl->heartbeat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             atomicSub(&P.ctl->outstanding, 1);
         }
         __syncthreads();
@@ -2306,6 +2502,7 @@ __global__ void init_kernel(ExecParams P, int restart, int n_root_shots, int roo
     for (int64_t i = gid; i < P.n_shots; i += stride) {
         if (!restart) {
             P.memory[i] = 0;
+            P.margins[i] = kInfBits;
             P.shot_perm[i] = (int32_t)i;
         }
     }
@@ -2348,6 +2545,7 @@ __global__ void init_kernel(ExecParams P, int restart, int n_root_shots, int roo
         ctl->n_initial = n_initial;
         for (int s = 0; s < ST_COUNT; ++s) ctl->stat[s] = 0;
         ctl->done_workers = 0;
+        ctl->heartbeat = 0;
     }
 }
 
@@ -2361,6 +2559,7 @@ __global__ void restart_kernel(ExecParams P, int n_wait)
         const int32_t s = P.waiting[i];
         P.shot_perm[i] = s;
         P.memory[s] = 0;
+        P.margins[s] = kInfBits;
     }
 }
 

@@ -1,6 +1,6 @@
 // Plain per-shot form: the conventional GPU execution the batched and
 // branched forms are measured against (Sec. III-C, the "GPU: Base" runs of
-// Sec. V-A). One shot at a time, one kernel launch per op over the whole
+// Sec. V-B). One shot at a time, one kernel launch per op over the whole
 // state, no batching, no fusion, no branching. Random decisions are taken
 // on the device by a one-workgroup kernel per random op (FP64 sums of the
 // per-block partials in a fixed order, the same Philox draws as the other
@@ -65,7 +65,7 @@ __device__ __forceinline__ A cmv(const double *m, double s, A a, A b, int row)
 }
 
 template <class R>
-__global__ void k_init(typename V2<R>::T *st, uint64_t namps, uint64_t *mem)
+__global__ void k_init(typename V2<R>::T *st, uint64_t namps, uint64_t *mem, uint64_t *marg)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kB + threadIdx.x;
     if (i < namps) {
@@ -74,7 +74,10 @@ __global__ void k_init(typename V2<R>::T *st, uint64_t namps, uint64_t *mem)
         z.y = 0;
         st[i] = z;
     }
-    if (i == 0) *mem = 0;
+    if (i == 0) {
+        *mem = 0;
+        *marg = kInfBits;
+    }
 }
 
 // 2x2 matrix on qubit q (matrix m, or the decided Kraus matrix when cell)
@@ -96,36 +99,67 @@ __global__ void k_mat1(typename V2<R>::T *st, uint64_t npairs, uint32_t q, const
     st[i1] = cmv<A, R>(m, s, a, b, 1);
 }
 
-// 4x4 matrix on (q0, q1); bit t of the matrix index is qubit q_t
-template <class R>
-__global__ void k_mat2(typename V2<R>::T *st, uint64_t nquads, uint32_t q0, uint32_t q1,
-                       const double *m, const Cell *cell, uint32_t mat_stride)
+// Dense 2^NQ x 2^NQ matrix on qubits q[0..NQ-1] (bit t of its row/column
+// index is qubit q[t]); the decided Kraus matrix when cell. One thread per
+// base index: it holds the 2^NQ amplitudes and writes each output row.
+template <class R, int NQ>
+__global__ void k_dense(typename V2<R>::T *st, uint64_t nbase, const DevOp *op, const double *m,
+                        const Cell *cell, uint32_t mat_stride)
 {
     using A = typename V2<R>::T;
+    constexpr int D = 1 << NQ;
     const uint64_t p = (uint64_t)blockIdx.x * kB + threadIdx.x;
-    if (p >= nquads) return;
+    if (p >= nbase) return;
     double s = 1.0;
     if (cell) {
         m += (size_t)cell->outcome * mat_stride;
         s = cell->scale;
     }
-    const uint32_t lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
-    const uint64_t base = ins0(ins0(p, lo), hi);
-    const uint64_t idx[4] = {base, base | (1ull << q0), base | (1ull << q1),
-                             base | (1ull << q0) | (1ull << q1)};
-    A v[4], o[4];
-    for (int a = 0; a < 4; ++a) v[a] = st[idx[a]];
-    for (int a = 0; a < 4; ++a) {
+    uint32_t q[NQ], sorted[NQ];
+    for (int t = 0; t < NQ; ++t) q[t] = sorted[t] = op->q[t];
+    for (int i = 0; i < NQ; ++i)
+        for (int j = 0; j + 1 < NQ - i; ++j)
+            if (sorted[j] > sorted[j + 1]) {
+                const uint32_t t = sorted[j];
+                sorted[j] = sorted[j + 1];
+                sorted[j + 1] = t;
+            }
+    uint64_t base = p;
+    for (int t = 0; t < NQ; ++t) base = ins0(base, sorted[t]);
+    A v[D];
+    for (int a = 0; a < D; ++a) {
+        uint64_t idx = base;
+        for (int t = 0; t < NQ; ++t) idx |= (uint64_t)((a >> t) & 1) << q[t];
+        v[a] = st[idx];
+    }
+    for (int a = 0; a < D; ++a) {
         R xr = 0, xi = 0;
-        for (int b = 0; b < 4; ++b) {
-            const R mr = (R)(m[2 * (4 * a + b)] * s), mi = (R)(m[2 * (4 * a + b) + 1] * s);
+        for (int b = 0; b < D; ++b) {
+            const R mr = (R)(m[2 * (D * a + b)] * s), mi = (R)(m[2 * (D * a + b) + 1] * s);
             xr += mr * v[b].x - mi * v[b].y;
             xi += mr * v[b].y + mi * v[b].x;
         }
-        o[a].x = xr;
-        o[a].y = xi;
+        uint64_t idx = base;
+        for (int t = 0; t < NQ; ++t) idx |= (uint64_t)((a >> t) & 1) << q[t];
+        A o;
+        o.x = xr;
+        o.y = xi;
+        st[idx] = o;
     }
-    for (int a = 0; a < 4; ++a) st[idx[a]] = o[a];
+}
+
+template <class R>
+static void launch_dense(typename V2<R>::T *st, int n, int nq, const DevOp *op, const double *m,
+                         const Cell *cell, uint32_t mat_stride, hipStream_t stream)
+{
+    const uint64_t nbase = (1ull << n) >> nq;
+    const dim3 g((unsigned)((nbase + kB - 1) / kB)), b(kB);
+    switch (nq) {
+    case 2: hipLaunchKernelGGL((k_dense<R, 2>), g, b, 0, stream, st, nbase, op, m, cell, mat_stride); break;
+    case 3: hipLaunchKernelGGL((k_dense<R, 3>), g, b, 0, stream, st, nbase, op, m, cell, mat_stride); break;
+    case 4: hipLaunchKernelGGL((k_dense<R, 4>), g, b, 0, stream, st, nbase, op, m, cell, mat_stride); break;
+    default: hipLaunchKernelGGL((k_dense<R, 5>), g, b, 0, stream, st, nbase, op, m, cell, mat_stride); break;
+    }
 }
 
 // CX (kind 0), CZ (1), SWAP (2)
@@ -172,17 +206,18 @@ __global__ void k_pauli_decide(uint64_t seed, uint64_t shot, uint32_t r, const d
 // (-i)^ny); nothing to do for the identity.
 template <class R>
 __global__ void k_pauli_apply(typename V2<R>::T *st, uint64_t namps, const DevRule *ru,
-                              const DevOp *op, const Cell *cell)
+                              const double *pool, const DevOp *op, const Cell *cell)
 {
     using A = typename V2<R>::T;
     const int d = cell->outcome;
-    if ((ru->ident_mask >> d) & 1u) return;
+    const uint32_t code = (uint32_t)pool[ru->codes + (uint32_t)d];  // x | z << 8 | ny << 16
+    if (code == 0) return;  // identity
     uint64_t xm = 0, zm = 0;
     for (int t = 0; t < op->nq; ++t) {
-        xm |= (uint64_t)((ru->xcode[d] >> t) & 1u) << op->q[t];
-        zm |= (uint64_t)((ru->zcode[d] >> t) & 1u) << op->q[t];
+        xm |= (uint64_t)((code >> t) & 1u) << op->q[t];
+        zm |= (uint64_t)((code >> (8 + t)) & 1u) << op->q[t];
     }
-    const uint32_t ny = ru->ny[d] & 3u;
+    const uint32_t ny = (code >> 16) & 3u;
     const uint64_t i = (uint64_t)blockIdx.x * kB + threadIdx.x;
     if (i >= namps) return;
     auto ph = [&](A v, uint64_t idx) {
@@ -242,32 +277,41 @@ __global__ void k_reduce(const typename V2<R>::T *st, int n, const DevOp *op, co
                 }
             }
         } else {
-            const uint32_t q0 = op->q[0], q1 = op->q[1];
-            const uint32_t lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
-            for (uint64_t p = gid; p < namps / 4; p += stride) {
-                const uint64_t base = ins0(ins0(p, lo), hi);
-                const uint64_t idx[4] = {base, base | (1ull << q0), base | (1ull << q1),
-                                         base | (1ull << q0) | (1ull << q1)};
-                double vr[4], vi[4];
-                for (int a = 0; a < 4; ++a) {
-                    const A v = st[idx[a]];
+            const int nq = (int)ru.nq, D = 1 << nq;
+            uint32_t q[kMaxDenseQ], sorted[kMaxDenseQ];
+            for (int t = 0; t < nq; ++t) q[t] = sorted[t] = op->q[t];
+            for (int i = 0; i < nq; ++i)
+                for (int j = 0; j + 1 < nq - i; ++j)
+                    if (sorted[j] > sorted[j + 1]) {
+                        const uint32_t t = sorted[j];
+                        sorted[j] = sorted[j + 1];
+                        sorted[j + 1] = t;
+                    }
+            for (uint64_t p = gid; p < (namps >> nq); p += stride) {
+                uint64_t base = p;
+                for (int t = 0; t < nq; ++t) base = ins0(base, sorted[t]);
+                double vr[1 << kMaxDenseQ], vi[1 << kMaxDenseQ];
+                for (int a = 0; a < D; ++a) {
+                    uint64_t idx = base;
+                    for (int t = 0; t < nq; ++t) idx |= (uint64_t)((a >> t) & 1) << q[t];
+                    const A v = st[idx];
                     vr[a] = v.x;
                     vi[a] = v.y;
                     acc[0] += vr[a] * vr[a] + vi[a] * vi[a];
                 }
                 for (int j = 0; j < nm && j < kMaxKraus; ++j) {
-                    const double *m = K + j * 32;
-                    double s = 0;
-                    for (int a = 0; a < 4; ++a) {
+                    const double *m = K + (size_t)j * D * D * 2;
+                    double sj = 0;
+                    for (int a = 0; a < D; ++a) {
                         double wr = 0, wi = 0;
-                        for (int b = 0; b < 4; ++b) {
-                            const double mr = m[2 * (4 * a + b)], mi = m[2 * (4 * a + b) + 1];
+                        for (int b = 0; b < D; ++b) {
+                            const double mr = m[2 * (D * a + b)], mi = m[2 * (D * a + b) + 1];
                             wr += mr * vr[b] - mi * vi[b];
                             wi += mr * vi[b] + mi * vr[b];
                         }
-                        s += wr * wr + wi * wi;
+                        sj += wr * wr + wi * wi;
                     }
-                    acc[1 + j] += s;
+                    acc[1 + j] += sj;
                 }
             }
         }
@@ -295,10 +339,21 @@ __global__ void k_reduce(const typename V2<R>::T *st, int n, const DevOp *op, co
     }
 }
 
+// Keep the smallest relative decision margin of the shot (bits of a
+// non-negative double).
+__device__ __forceinline__ void keep_margin(uint64_t *marg, double m)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, m);
+    if (b < *marg) *marg = b;
+}
+
 // Sum the partials in block order, draw, choose (first running sum above
-// u*N, else the last candidate with weight), record measured bits.
+// u*N, else the last candidate with weight), record measured bits and the
+// decision margin. N is the Kraus channel's norm sum, or for a measurement
+// the sum of its outcome probabilities in outcome order.
 __global__ void k_decide(const double *partial, int nblocks, int cnt, uint64_t seed, uint64_t shot,
-                         const DevOp *op, Cell *cell, uint64_t *mem, double ro01, double ro10)
+                         const DevOp *op, Cell *cell, uint64_t *mem, uint64_t *marg, double ro01,
+                         double ro10)
 {
     // sum the per-block partials: each thread a strided share, then a
     // fixed-order tree over the threads (the same order on every call)
@@ -320,14 +375,28 @@ __global__ void k_decide(const double *partial, int nblocks, int cnt, uint64_t s
     __syncthreads();
     if (t != 0) return;
     const double u = philox_u01(seed, shot, op->r, 0);
-    const double x = u * red[0];
-    double run = 0;
+    double N = red[0];
+    if (op->kind == DK_MEASURE) {
+        N = 0;
+        for (int t = 0; t < cnt; ++t) N += red[1 + t];
+    }
+    const double x = u * N;
+    double run = 0, prev = 0;
     int o = -1, last = 0;
     for (int t = 0; t < cnt; ++t) {
         if (red[1 + t] > 0) last = t;
+        prev = run;
         run += red[1 + t];
         if (x < run) { o = t; break; }
     }
+    double mg = 0.0;  // the rounding fall-back is a tie
+    if (o >= 0 && N > 0) {
+        mg = __builtin_inf();
+        if (o > 0) mg = fmin(mg, x - prev);
+        if (o < cnt - 1) mg = fmin(mg, run - x);
+        mg /= N;
+    }
+    keep_margin(marg, mg);
     if (o < 0) o = last;
     cell->outcome = o;
     cell->scale = 1.0 / sqrt(red[1 + o]);
@@ -400,7 +469,7 @@ __global__ void k_chunks(const typename V2<R>::T *st, uint64_t namps, double *ch
 template <class R>
 __global__ void k_sample(const typename V2<R>::T *st, uint64_t namps, const double *chunk,
                          uint64_t nchunks, int n, uint64_t seed, uint64_t shot, const DevOp *op,
-                         uint64_t *mem, double ro01, double ro10)
+                         uint64_t *mem, uint64_t *marg, double ro01, double ro10)
 {
     if (threadIdx.x != 0) return;
     double N = 0;
@@ -417,15 +486,28 @@ __global__ void k_sample(const typename V2<R>::T *st, uint64_t namps, const doub
     const bool fell_through = b == nchunks;
     if (fell_through) b = lastb;
     const uint64_t e0 = b * kB, e1 = (b + 1) * kB < namps ? (b + 1) * kB : namps;
+    // margin: the chunk boundaries that chose chunk b, then the boundaries
+    // of the chosen entry (the state's last entry has no upper boundary)
+    double mg = __builtin_inf();
+    if (b > 0) mg = fmin(mg, x - run);
+    if (b + 1 < nchunks) mg = fmin(mg, run + chunk[b] - x);
     uint64_t idx = e0, lastnz = e0;
     bool found = false;
     for (uint64_t e = e0; e < e1; ++e) {
         const double w = (double)st[e].x * st[e].x + (double)st[e].y * st[e].y;
         if (w > 0) lastnz = e;
+        const double before = run;
         run += w;
-        if (!fell_through && x < run) { idx = e; found = true; break; }
+        if (!fell_through && x < run) {
+            idx = e;
+            found = true;
+            if (e > e0) mg = fmin(mg, x - before);
+            if (e + 1 < namps) mg = fmin(mg, run - x);
+            break;
+        }
     }
     if (!found) idx = lastnz;
+    keep_margin(marg, found && N > 0 ? mg / N : 0.0);
     uint64_t m = *mem;
     for (int q = 0; q < n; ++q) {
         uint64_t bit = (idx >> q) & 1ull;
@@ -449,8 +531,8 @@ template <class R>
 static hipError_t plain_run_t(const DevOp *ops, const DevOp *hops, int n_ops, const DevRule *rules,
                               const DevRule *hrules, const double *pool, int n, uint64_t n_shots,
                               uint64_t shot_base, uint64_t seed, void *state, uint64_t *memory,
-                              double *partial, int red_blocks, double *chunk, void *cellp,
-                              double ro01, double ro10, hipStream_t st)
+                              uint64_t *margins, double *partial, int red_blocks, double *chunk,
+                              void *cellp, double ro01, double ro10, hipStream_t st)
 {
     using A = typename V2<R>::T;
     A *S = (A *)state;
@@ -464,7 +546,8 @@ static hipError_t plain_run_t(const DevOp *ops, const DevOp *hops, int n_ops, co
     for (uint64_t s = 0; s < n_shots; ++s) {
         const uint64_t shot = shot_base + s;
         uint64_t *mem = memory + s;
-        hipLaunchKernelGGL(k_init<R>, dim3(g1), dim3(kB), 0, st, S, namps, mem);
+        uint64_t *marg = margins + s;
+        hipLaunchKernelGGL(k_init<R>, dim3(g1), dim3(kB), 0, st, S, namps, mem, marg);
         for (int j = 0; j < n_ops; ++j) {
             const DevOp &h = hops[j];
             const DevOp *d = ops + j;
@@ -473,9 +556,8 @@ static hipError_t plain_run_t(const DevOp *ops, const DevOp *hops, int n_ops, co
                 hipLaunchKernelGGL(k_mat1<R>, dim3(g2), dim3(kB), 0, st, S, namps / 2, h.q[0],
                                    pool + h.mat, (const Cell *)nullptr, 0u);
                 break;
-            case DK_MAT2:
-                hipLaunchKernelGGL(k_mat2<R>, dim3(g4), dim3(kB), 0, st, S, namps / 4, h.q[0],
-                                   h.q[1], pool + h.mat, (const Cell *)nullptr, 0u);
+            case DK_MATK:
+                launch_dense<R>(S, n, h.nq, d, pool + h.mat, nullptr, 0u, st);
                 break;
             case DK_CX:
             case DK_CZ:
@@ -488,7 +570,7 @@ static hipError_t plain_run_t(const DevOp *ops, const DevOp *hops, int n_ops, co
                 hipLaunchKernelGGL(k_pauli_decide, dim3(1), dim3(1), 0, st, seed, shot, h.r,
                                    pool + hr.thr, (int)hr.n_terms, cell);
                 hipLaunchKernelGGL(k_pauli_apply<R>, dim3(g1), dim3(kB), 0, st, S, namps,
-                                   rules + h.rule, d, (const Cell *)cell);
+                                   rules + h.rule, pool, d, (const Cell *)cell);
                 break;
             }
             case DK_KRAUS: {
@@ -496,14 +578,13 @@ static hipError_t plain_run_t(const DevOp *ops, const DevOp *hops, int n_ops, co
                 hipLaunchKernelGGL(k_reduce<R>, dim3(red_blocks), dim3(kB), 0, st, (const A *)S, n, d,
                                    rules, pool, partial);
                 hipLaunchKernelGGL(k_decide, dim3(1), dim3(kB), 0, st, (const double *)partial,
-                                   red_blocks, (int)hr.n_terms, seed, shot, d, cell, mem, ro01, ro10);
+                                   red_blocks, (int)hr.n_terms, seed, shot, d, cell, mem, marg, ro01, ro10);
                 const uint32_t dim = 1u << hr.nq;
                 if (hr.nq == 1)
                     hipLaunchKernelGGL(k_mat1<R>, dim3(g2), dim3(kB), 0, st, S, namps / 2, h.q[0],
                                        pool + hr.mats, (const Cell *)cell, dim * dim * 2);
                 else
-                    hipLaunchKernelGGL(k_mat2<R>, dim3(g4), dim3(kB), 0, st, S, namps / 4, h.q[0],
-                                       h.q[1], pool + hr.mats, (const Cell *)cell, dim * dim * 2);
+                    launch_dense<R>(S, n, (int)hr.nq, d, pool + hr.mats, cell, dim * dim * 2, st);
                 break;
             }
             case DK_MEASURE: {
@@ -512,13 +593,13 @@ static hipError_t plain_run_t(const DevOp *ops, const DevOp *hops, int n_ops, co
                                        chunk);
                     hipLaunchKernelGGL(k_sample<R>, dim3(1), dim3(64), 0, st, (const A *)S, namps,
                                        (const double *)chunk, (uint64_t)g1, n, seed, shot, d, mem,
-                                       ro01, ro10);
+                                       marg, ro01, ro10);
                     break;
                 }
                 hipLaunchKernelGGL(k_reduce<R>, dim3(red_blocks), dim3(kB), 0, st, (const A *)S, n, d,
                                    rules, pool, partial);
                 hipLaunchKernelGGL(k_decide, dim3(1), dim3(kB), 0, st, (const double *)partial,
-                                   red_blocks, 1 << h.nq, seed, shot, d, cell, mem, ro01, ro10);
+                                   red_blocks, 1 << h.nq, seed, shot, d, cell, mem, marg, ro01, ro10);
                 hipLaunchKernelGGL(k_collapse<R>, dim3(g1), dim3(kB), 0, st, S, namps, d,
                                    (const Cell *)cell);
                 if (h.flags & DF_RESET)
@@ -539,13 +620,15 @@ static hipError_t plain_run_t(const DevOp *ops, const DevOp *hops, int n_ops, co
 extern "C" hipError_t svb_plain_run(int is_c128, const DevOp *ops, const DevOp *hops, int n_ops,
                                     const DevRule *rules, const DevRule *hrules, const double *pool,
                                     int n, uint64_t n_shots, uint64_t shot_base, uint64_t seed,
-                                    void *state, uint64_t *memory, double *partial, int red_blocks,
-                                    double *chunk, void *cell, double ro01, double ro10,
-                                    hipStream_t st)
+                                    void *state, uint64_t *memory, uint64_t *margins,
+                                    double *partial, int red_blocks, double *chunk, void *cell,
+                                    double ro01, double ro10, hipStream_t st)
 {
     if (is_c128)
         return plain_run_t<double>(ops, hops, n_ops, rules, hrules, pool, n, n_shots, shot_base, seed,
-                                   state, memory, partial, red_blocks, chunk, cell, ro01, ro10, st);
+                                   state, memory, margins, partial, red_blocks, chunk, cell, ro01,
+                                   ro10, st);
     return plain_run_t<float>(ops, hops, n_ops, rules, hrules, pool, n, n_shots, shot_base, seed,
-                              state, memory, partial, red_blocks, chunk, cell, ro01, ro10, st);
+                              state, memory, margins, partial, red_blocks, chunk, cell, ro01, ro10,
+                              st);
 }

@@ -12,16 +12,22 @@ constexpr int kMaxPassGroups = 64;   // register groups in one sweep
 constexpr int kMaxPassUops = 384;    // register micro-ops in one sweep
 constexpr int kPassMatBytes = 6144;  // LDS bytes for the fused 2x2 matrices of one sweep
 constexpr int kMaxKraus = 16;        // matrices per Kraus channel
+constexpr int kMaxDenseQ = 5;        // qubits of a dense matrix (unitary, Kraus channel)
+constexpr int kMaxPauliQ = 5;        // qubits of a Pauli channel
+constexpr int kMaxPauliTerms = 1024; // terms of a Pauli channel (4^5)
 constexpr int kMaxMeasQ = 4;         // qubits of a non-terminal measure
 constexpr int kMaxRed = 1 + 16;      // norm + up to 16 outcome sums
 constexpr int kCoalesceQ = 4;        // low qubits always inside a tile
+constexpr double kNearTie = 1e-9;    // relative decision margin counted as a near-tie
+constexpr uint64_t kInfBits = 0x7FF0000000000000ull;  // +inf as double bits
 constexpr uint32_t kRunMask = (1u << kCoalesceQ) - 1;  // contiguous run of a tile in HBM
 constexpr int kMaxTileQ = 14;
 
 // Device op kinds (after noise-site expansion).
 enum DevKind : uint16_t {
     DK_MAT1 = 1,     // 2x2 matrix on lb[0]
-    DK_MAT2 = 2,     // 4x4 matrix on (lb[0], lb[1]); index bit t <-> lb[t]
+    DK_MATK = 2,     // dense 2^nq x 2^nq matrix (nq = 2..5) on lb[0..nq-1];
+                     // bit t of its row/column index <-> lb[t]
     DK_CX = 3,       // control lb[0], target lb[1]
     DK_CZ = 4,
     DK_SWAP = 5,
@@ -81,10 +87,9 @@ struct DevRule {
     uint32_t mats;       // Kraus: pool offset of matrices (fp64 complex)
     uint32_t diag_mm;    // Kraus: every K^dagger K is diagonal
     double lam_min0;     // Kraus: smallest eigenvalue of K0^dagger K0
-    uint32_t xcode[16];  // Pauli term: bit t set if X or Y on gate qubit t
-    uint32_t zcode[16];  // Pauli term: bit t set if Z or Y on gate qubit t
-    uint32_t ny[16];     // Pauli term: number of Y
-    uint32_t ident_mask; // Pauli: bit j set if term j is the identity
+    uint32_t codes;      // Pauli: pool offset of the term codes, one double per term
+                         // holding x | z << 8 | ny << 16 (bit t of x: X or Y on gate
+                         // qubit t; of z: Z or Y; ny: number of Y; 0: identity)
     uint32_t scalar_mask;// Kraus: bit j set if matrix j is a multiple of the identity
 };
 
@@ -109,7 +114,7 @@ struct BranchRec {
 
 enum CtlStat {
     ST_PASSES = 0, ST_BYTES, ST_REDUCTIONS, ST_BRANCHES, ST_WAITING,
-    ST_FLOPS, ST_SPLITS, ST_GROUPS, ST_UOPS, ST_COUNT
+    ST_FLOPS, ST_SPLITS, ST_GROUPS, ST_UOPS, ST_NEARTIES, ST_COUNT
 };
 
 struct Control {
@@ -123,7 +128,8 @@ struct Control {
     uint32_t n_initial;     // records present at launch
     unsigned long long stat[ST_COUNT];
     uint32_t done_workers;
-    uint32_t pad[7];
+    uint32_t heartbeat;     // bumped by every workgroup at each sweep and record end
+    uint32_t pad[6];
 };
 
 constexpr uint32_t kErrTimeout = 1;
@@ -149,11 +155,16 @@ struct ExecParams {
     int32_t *free_slots;
     int32_t *waiting;
     void *dump;              // normalised state of dump_shot (complex)
+    uint64_t *margins;       // per shot: bits of its smallest relative decision margin
+                             // (a non-negative double, +inf without a decision)
     uint64_t seed;
     uint64_t shot_base;      // global id of local shot 0 (Philox counter)
     int64_t n_shots;
     int64_t dump_shot;
-    unsigned long long spin_limit;   // wall-clock ticks
+    unsigned long long spin_limit;   // wall-clock ticks a work-queue wait may last
+                                     // without any workgroup making progress
+    int32_t spin_elapsed;    // 1: the bound counts from the start of the wait,
+                             // whatever the other workgroups do
     double ro01, ro10;
     int32_t n_ops;
     int32_t n_qubits;

@@ -39,8 +39,8 @@ size_t svb_counts_temp_bytes(int64_t n);
 hipError_t svb_plain_run(int is_c128, const DevOp *ops, const DevOp *hops, int n_ops,
                          const DevRule *rules, const DevRule *hrules, const double *pool, int n,
                          uint64_t n_shots, uint64_t shot_base, uint64_t seed, void *state,
-                         uint64_t *memory, double *partial, int red_blocks, double *chunk,
-                         void *cell, double ro01, double ro10, hipStream_t st);
+                         uint64_t *memory, uint64_t *margins, double *partial, int red_blocks,
+                         double *chunk, void *cell, double ro01, double ro10, hipStream_t st);
 }
 
 // ------------------------------------------------------------------ errors
@@ -66,6 +66,19 @@ static sv_status fail(sv_status s, const char *fmt, ...)
 
 static uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
+// HIP events time a run; a handle without events (the no-allocation entry
+// point) skips the timing and waits on its stream instead.
+static hipError_t ev_record(hipEvent_t e, hipStream_t s) { return e ? hipEventRecord(e, s) : hipSuccess; }
+static hipError_t ev_wait(hipEvent_t e, hipStream_t s)
+{
+    return e ? hipEventSynchronize(e) : hipStreamSynchronize(s);
+}
+static hipError_t ev_ms(float *ms, hipEvent_t a, hipEvent_t b)
+{
+    *ms = 0;
+    return (a && b) ? hipEventElapsedTime(ms, a, b) : hipSuccess;
+}
+
 constexpr int kPlainRedBlocks = 1024;  // blocks of a plain-mode reduction
 
 // ------------------------------------------------------------------ handle
@@ -79,6 +92,7 @@ struct sv_batch {
     int64_t program_bytes = 8 << 20;
     int64_t dump_shot = -1;
     int64_t spin_ms = 300000;
+    int64_t spin_elapsed = 0;         // 1: the wait bound counts elapsed time, not stalled time
     int64_t shot_offset = 0;
     // derived
     int tile_q = 0, resident = 0, workers = 0, slots = 0;
@@ -90,13 +104,15 @@ struct sv_batch {
     int64_t wallclock_khz = 100000;
     int64_t auto_slots = 0;            // branch mode's automatic slot count, fixed at first sizing
     int64_t auto_workers = 0;          // batch mode's memory-bounded worker count, same
+    uint64_t arena_cap = 0;            // >0: workers and slots are fitted to an arena this size
+    bool no_counts = false;            // no room reserved for the counts histogram
     // arena
     bool attached = false;
     char *arena = nullptr;
     uint64_t arena_bytes = 0;
     hipStream_t stream = nullptr;
     struct Layout {
-        uint64_t prog, memory, perm, tmp, waiting, queue, ready, ctl, free_slots, tile_sums,
+        uint64_t prog, memory, margins, perm, tmp, waiting, queue, ready, ctl, free_slots, tile_sums,
             dump, counts_tmp, keys_sorted, uniq, cnt, nuniq, slots, total;
     } lay{};
     // results
@@ -222,6 +238,7 @@ static void layout(sv_batch *b)
     const uint64_t S = (uint64_t)b->shots;
     L.prog = take((uint64_t)b->program_bytes);
     L.memory = take(S * 8);
+    L.margins = take(S * 8);
     L.perm = take(S * 4);
     L.tmp = take(S * 4);
     L.waiting = take(S * 4);
@@ -235,10 +252,10 @@ static void layout(sv_batch *b)
         ts = (uint64_t)kPlainRedBlocks * 17 * 8 + (((1ull << b->n) + 255) / 256) * 8 + 64;
     L.tile_sums = take(ts);
     L.dump = take(b->dump_shot >= 0 ? (16ull << b->n) : 8);
-    L.counts_tmp = take(svb_counts_temp_bytes((int64_t)S));
-    L.keys_sorted = take(S * 8);
-    L.uniq = take(S * 8);
-    L.cnt = take(S * 4);
+    L.counts_tmp = take(b->no_counts ? 8 : svb_counts_temp_bytes((int64_t)S));
+    L.keys_sorted = take(b->no_counts ? 8 : S * 8);
+    L.uniq = take(b->no_counts ? 8 : S * 8);
+    L.cnt = take(b->no_counts ? 8 : S * 4);
     L.nuniq = take(8);
     L.slots = take((uint64_t)b->slots * state_bytes(b));
     L.total = off;
@@ -323,8 +340,9 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
                 const auto *pc = (const sv_pauli_channel *)nr.channel;
                 R.nq = (int)pc->nq;
                 R.n_terms = (int)pc->n_terms;
-                if (R.nq < 1 || R.nq > 2) return fail(SV_EUNSUPPORTED, "rule %u: Pauli channel on %d qubits", r, R.nq);
-                if (R.n_terms < 1 || R.n_terms > 16) return fail(SV_EINVAL, "rule %u: %d Pauli terms (1..16)", r, R.n_terms);
+                if (R.nq < 1 || R.nq > kMaxPauliQ) return fail(SV_EUNSUPPORTED, "rule %u: Pauli channel on %d qubits (1..%d)", r, R.nq, kMaxPauliQ);
+                if (R.n_terms < 1 || R.n_terms > kMaxPauliTerms) return fail(SV_EINVAL, "rule %u: %d Pauli terms (1..%d)", r, R.n_terms, kMaxPauliTerms);
+                if (!pc->prob || !pc->pauli) return fail(SV_EINVAL, "rule %u: NULL table", r);
                 double sum = 0;
                 for (int j = 0; j < R.n_terms; ++j) {
                     const double p = pc->prob[j];
@@ -342,7 +360,8 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
                 const auto *kc = (const sv_kraus_channel *)nr.channel;
                 R.nq = (int)kc->nq;
                 R.n_terms = (int)kc->n_mats;
-                if (R.nq < 1 || R.nq > 2) return fail(SV_EUNSUPPORTED, "rule %u: Kraus channel on %d qubits", r, R.nq);
+                if (R.nq < 1 || R.nq > kMaxDenseQ) return fail(SV_EUNSUPPORTED, "rule %u: Kraus channel on %d qubits (1..%d)", r, R.nq, kMaxDenseQ);
+                if (!kc->mats) return fail(SV_EINVAL, "rule %u: NULL matrices", r);
                 if (R.n_terms < 1 || R.n_terms > kMaxKraus) return fail(SV_EUNSUPPORTED, "rule %u: %d Kraus matrices (1..%d)", r, R.n_terms, kMaxKraus);
                 const int d = 1 << R.nq;
                 std::vector<cd> sum(d * d, 0.0);
@@ -392,8 +411,9 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
         if (gate && k != SV_OP_UNITARY && op.nq != (uint32_t)nq && op.nq != 0)
             return fail(SV_EINVAL, "op %zu: kind %u acts on %d qubits, nq=%u", i, k, nq, op.nq);
         if (nq < 1) return fail(SV_EINVAL, "op %zu: no qubits", i);
-        if (k == SV_OP_UNITARY && (nq > 2 || !op.mat))
-            return fail(nq > 2 ? SV_EUNSUPPORTED : SV_EINVAL, "op %zu: unitary on %d qubits (1..2, mat required)", i, nq);
+        if (k == SV_OP_UNITARY && (nq > kMaxDenseQ || !op.mat))
+            return fail(nq > kMaxDenseQ ? SV_EUNSUPPORTED : SV_EINVAL,
+                        "op %zu: unitary on %d qubits (1..%d, mat required)", i, nq, kMaxDenseQ);
         const uint32_t *qs = nq > SV_MAX_INLINE ? op.q_ext : op.q;
         const uint32_t *cs = nq > SV_MAX_INLINE ? op.c_ext : op.c;
         if (!qs) return fail(SV_EINVAL, "op %zu: qubit list is NULL", i);
@@ -440,8 +460,7 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
         if (gate) {
             for (size_t r = 0; r < rules.size(); ++r) {
                 if (k >= 64 || !((rules[r].mask >> k) & 1)) continue;
-                if (rules[r].nq != nq)
-                    return fail(SV_EINVAL, "op %zu: rule %zu acts on %d qubits, gate on %d", i, r, rules[r].nq, nq);
+                if (rules[r].nq != nq) continue;  // a rule attaches to gates of its own width only
                 XOp ch;
                 ch.kind = rules[r].kraus ? -2 : -1;
                 ch.rule = (int)r;
@@ -487,11 +506,15 @@ static bool op_ordered(const XOp &x)
            x.kind == SV_OP_MEASURE_RESET || x.kind == SV_OP_BFUNC || x.cond_mask != 0;
 }
 
-static bool op_fallback(const XOp &x, const std::vector<Rule> &rules)
+// Ops that run as LDS sweeps rather than in register groups: measurements,
+// dense matrices on two or more qubits (unitaries, Kraus channels), and
+// Pauli channels on more qubits than a register group holds (r).
+static bool op_fallback(const XOp &x, const std::vector<Rule> &rules, int r)
 {
     if (x.kind == SV_OP_MEASURE || x.kind == SV_OP_RESET || x.kind == SV_OP_MEASURE_RESET) return true;
-    if (x.kind == SV_OP_UNITARY && x.q.size() == 2) return true;
-    if (x.kind == -2 && rules[x.rule].nq == 2) return true;
+    if (x.kind == SV_OP_UNITARY && x.q.size() >= 2) return true;
+    if (x.kind == -2 && rules[x.rule].nq >= 2) return true;
+    if (x.kind == -1 && rules[x.rule].nq > r) return true;
     return false;
 }
 
@@ -528,15 +551,15 @@ static int gf2_rank_add(uint32_t basis[6], uint32_t v)
 // taking a gate into a pass or group while deferring its channel would
 // split the fused one-qubit factor of that qubit into two micro-ops.
 static size_t unit_end(const std::vector<XOp> &xo, const std::vector<uint32_t> &list, size_t idx,
-                       const std::vector<Rule> &rules, bool groups)
+                       const std::vector<Rule> &rules, bool groups, int r)
 {
     const XOp &g = xo[list[idx]];
     size_t e = idx + 1;
-    if (g.kind < 0 || !is_gate_kind((uint32_t)g.kind) || (groups && op_fallback(g, rules))) return e;
+    if (g.kind < 0 || !is_gate_kind((uint32_t)g.kind) || (groups && op_fallback(g, rules, r))) return e;
     const uint32_t m = qmask_of(g);
     while (e < list.size() && list[e] == list[e - 1] + 1) {
         const XOp &x = xo[list[e]];
-        if (x.kind >= 0 || (qmask_of(x) & ~m) || (groups && op_fallback(x, rules))) break;
+        if (x.kind >= 0 || (qmask_of(x) & ~m) || (groups && op_fallback(x, rules, r))) break;
         ++e;
     }
     return e;
@@ -581,7 +604,7 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
             for (size_t idx = 0; idx < grem.size();) {
                 const uint32_t j = grem[idx];
                 const XOp &x = xo[j];
-                const bool fb = !use_groups || op_fallback(x, rules);
+                const bool fb = !use_groups || op_fallback(x, rules, r);
                 if (fb) {
                     const uint32_t m = qmask_of(x);
                     const bool ord = op_ordered(x);
@@ -598,7 +621,7 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
                     ++idx;
                     continue;
                 }
-                const size_t e = unit_end(xo, grem, idx, rules, true);
+                const size_t e = unit_end(xo, grem, idx, rules, true, r);
                 uint32_t m = 0;
                 bool ord = false;
                 for (size_t t = idx; t < e; ++t) {
@@ -675,7 +698,7 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
         uint32_t T = base_mask, blocked = 0;
         bool ord_blocked = false;
         for (size_t idx = 0; idx < remaining.size();) {
-            const size_t e = unit_end(xo, remaining, idx, rules, false);
+            const size_t e = unit_end(xo, remaining, idx, rules, false, r);
             if (sel.size() + (e - idx) > (size_t)kMaxPassOps) {
                 rest.insert(rest.end(), remaining.begin() + idx, remaining.end());
                 break;
@@ -740,6 +763,8 @@ static void rule_dev(const Rule &R, std::vector<double> &pool, DevRule &d)
             run += R.prob[j];
             pool.push_back(run);
         }
+        // term codes x | z << 8 | ny << 16, one double each (exact integers)
+        d.codes = (uint32_t)pool.size();
         for (int j = 0; j < R.n_terms; ++j) {
             uint32_t x = 0, z = 0, ny = 0;
             for (int t = 0; t < R.nq; ++t) {
@@ -748,10 +773,7 @@ static void rule_dev(const Rule &R, std::vector<double> &pool, DevRule &d)
                 if (c == 3 || c == 2) z |= 1u << t;
                 if (c == 2) ++ny;
             }
-            d.xcode[j] = x;
-            d.zcode[j] = z;
-            d.ny[j] = ny;
-            if (x == 0 && z == 0) d.ident_mask |= 1u << j;
+            pool.push_back((double)(x | (z << 8) | (ny << 16)));
         }
     } else {
         d.mats = (uint32_t)pool.size();
@@ -869,6 +891,9 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
     } else if (k == "spin_limit_ms") {
         if (v < 1) return fail(SV_EINVAL, "spin_limit_ms %lld", (long long)v);
         b->spin_ms = v;
+    } else if (k == "spin_elapsed") {
+        if (v < 0 || v > 1) return fail(SV_EINVAL, "spin_elapsed %lld (0 or 1)", (long long)v);
+        b->spin_elapsed = v;
     } else {
         return fail(SV_EINVAL, "unknown option '%s'", key);
     }
@@ -921,6 +946,7 @@ static sv_status run_empty(sv_batch *b)
     ExecParams P;
     std::memset(&P, 0, sizeof P);
     P.memory = (uint64_t *)(A + L.memory);
+    P.margins = (uint64_t *)(A + L.margins);
     P.shot_perm = (int32_t *)(A + L.perm);
     P.queue = (BranchRec *)(A + L.queue);
     P.ready = (uint32_t *)(A + L.ready);
@@ -928,17 +954,17 @@ static sv_status run_empty(sv_batch *b)
     P.free_slots = (int32_t *)(A + L.free_slots);
     P.n_shots = b->shots;
     P.queue_cap = (int32_t)b->shots;
-    HIPCHK(hipEventRecord(b->ev0, b->stream));
+    HIPCHK(ev_record(b->ev0, b->stream));
     HIPCHK(svb_launch_init(&P, 0, (int)b->shots, -1, 0, b->stream));
     if (b->dump_shot >= 0) {
         static const double one = 1.0;
         HIPCHK(hipMemsetAsync(A + L.dump, 0, 16ull << b->n, b->stream));
         HIPCHK(hipMemcpyAsync(A + L.dump, &one, sizeof one, hipMemcpyHostToDevice, b->stream));
     }
-    HIPCHK(hipEventRecord(b->ev1, b->stream));
-    HIPCHK(hipEventSynchronize(b->ev1));
+    HIPCHK(ev_record(b->ev1, b->stream));
+    HIPCHK(ev_wait(b->ev1, b->stream));
     float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    HIPCHK(ev_ms(&ms, b->ev0, b->ev1));
     sv_stats &st = b->stats;
     std::memset(&st, 0, sizeof st);
     st.kernel_ms = ms;
@@ -995,6 +1021,18 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
                         x.q.size(), kMaxMeasQ);
     }
     if (!b->attached) return fail(SV_ESTATE, "no arena attached");
+    // a streamed tile holds qubits 0..3 and the op's qubits
+    if (!b->resident && b->mode != SV_MODE_PLAIN) {
+        for (size_t j = 0; j < xo.size(); ++j) {
+            const XOp &x = xo[j];
+            const bool is_meas = x.kind == SV_OP_MEASURE || x.kind == SV_OP_RESET || x.kind == SV_OP_MEASURE_RESET;
+            if (is_meas && terminal && j + 1 == xo.size()) continue;
+            const int w = __builtin_popcount(qmask_of(x) | kRunMask);
+            if (w > b->tile_q)
+                return fail(SV_EUNSUPPORTED, "op %zu: its qubits and qubits 0..%d span %d qubits, "
+                            "more than the %d-qubit tile", j, kCoalesceQ - 1, w, b->tile_q);
+        }
+    }
 
     // device program
     Plan plan;
@@ -1079,7 +1117,7 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
             d.flags |= DF_PARAM;       // matrices of every set follow the base pool
             d.mat = (uint32_t)(x.u3_index * 8);  // rebased below
         } else {
-            d.kind = x.q.size() == 1 ? DK_MAT1 : DK_MAT2;
+            d.kind = x.q.size() == 1 ? DK_MAT1 : DK_MATK;
             d.mat = (uint32_t)pool.size();
             bool diag = x.q.size() == 1 && x.mat[1] == 0.0 && x.mat[2] == 0.0;
             if (diag) d.flags |= DF_DIAG;
@@ -1142,6 +1180,7 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     P.shot_perm = (int32_t *)(A + L.perm);
     P.shot_tmp = (int32_t *)(A + L.tmp);
     P.memory = (uint64_t *)(A + L.memory);
+    P.margins = (uint64_t *)(A + L.margins);
     P.queue = (BranchRec *)(A + L.queue);
     P.ready = (uint32_t *)(A + L.ready);
     P.ctl = (Control *)(A + L.ctl);
@@ -1153,6 +1192,7 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     P.n_shots = b->shots;
     P.dump_shot = b->dump_shot;
     P.spin_limit = (unsigned long long)b->spin_ms * (unsigned long long)b->wallclock_khz;
+    P.spin_elapsed = (int32_t)b->spin_elapsed;
     P.ro01 = ro01;
     P.ro10 = ro10;
     P.n_ops = (int32_t)dops.size();
@@ -1173,17 +1213,18 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
         double *scratch = (double *)(A + L.tile_sums);
         double *chunk = scratch + (size_t)kPlainRedBlocks * 17;
         void *cell = chunk + (((1ull << n) + 255) / 256);
-        HIPCHK(hipEventRecord(b->ev0, b->stream));
-        HIPCHK(hipEventRecord(b->ev2, b->stream));
+        HIPCHK(ev_record(b->ev0, b->stream));
+        HIPCHK(ev_record(b->ev2, b->stream));
         HIPCHK(svb_plain_run(b->dtype == SV_C128, P.ops, dops.data(), P.n_ops, P.rules, drules.data(),
                              P.pool, n, (uint64_t)b->shots, P.shot_base, seed, P.slots, P.memory,
-                             scratch, kPlainRedBlocks, chunk, cell, ro01, ro10, b->stream));
-        HIPCHK(hipEventRecord(b->ev3, b->stream));
-        HIPCHK(hipEventRecord(b->ev1, b->stream));
-        HIPCHK(hipEventSynchronize(b->ev1));
+                             P.margins, scratch, kPlainRedBlocks, chunk, cell, ro01, ro10,
+                             b->stream));
+        HIPCHK(ev_record(b->ev3, b->stream));
+        HIPCHK(ev_record(b->ev1, b->stream));
+        HIPCHK(ev_wait(b->ev1, b->stream));
         float ms = 0, ems = 0;
-        HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
-        HIPCHK(hipEventElapsedTime(&ems, b->ev2, b->ev3));
+        HIPCHK(ev_ms(&ms, b->ev0, b->ev1));
+        HIPCHK(ev_ms(&ems, b->ev2, b->ev3));
         sv_stats &st = b->stats;
         std::memset(&st, 0, sizeof st);
         st.kernel_ms = ms;
@@ -1218,19 +1259,19 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     const int n_free = branch ? (b->resident ? b->slots : b->slots - 1) : 0;
     uint64_t acc[ST_COUNT] = {0};
     uint64_t restarts = 0;
-    HIPCHK(hipEventRecord(b->ev0, b->stream));
+    HIPCHK(ev_record(b->ev0, b->stream));
     HIPCHK(svb_launch_init(&P, 0, (int)b->shots, root_slot, n_free, b->stream));
     double exec_ms = 0;
     uint32_t exec_launches = 0;
     for (;;) {
-        HIPCHK(hipEventRecord(b->ev2, b->stream));
+        HIPCHK(ev_record(b->ev2, b->stream));
         HIPCHK(svb_launch_exec(&P, b->dtype == SV_C128, b->reg_bits, b->workers, b->stream));
-        HIPCHK(hipEventRecord(b->ev3, b->stream));
+        HIPCHK(ev_record(b->ev3, b->stream));
         Control ctl;
         HIPCHK(hipMemcpyAsync(&ctl, P.ctl, sizeof ctl, hipMemcpyDeviceToHost, b->stream));
         HIPCHK(hipStreamSynchronize(b->stream));
         float lms = 0;
-        HIPCHK(hipEventElapsedTime(&lms, b->ev2, b->ev3));
+        HIPCHK(ev_ms(&lms, b->ev2, b->ev3));
         exec_ms += lms;
         ++exec_launches;
         if (ctl.error) return fail(SV_EDEVICE, "device executor failed (flags 0x%x)", ctl.error);
@@ -1240,10 +1281,10 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
         HIPCHK(svb_launch_restart(&P, (int)ctl.wait_count, b->stream));
         HIPCHK(svb_launch_init(&P, 1, (int)ctl.wait_count, root_slot, n_free, b->stream));
     }
-    HIPCHK(hipEventRecord(b->ev1, b->stream));
-    HIPCHK(hipEventSynchronize(b->ev1));
+    HIPCHK(ev_record(b->ev1, b->stream));
+    HIPCHK(ev_wait(b->ev1, b->stream));
     float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    HIPCHK(ev_ms(&ms, b->ev0, b->ev1));
 
     sv_stats &st = b->stats;
     std::memset(&st, 0, sizeof st);
@@ -1265,6 +1306,7 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     st.exec_ms = exec_ms;
     st.groups = acc[ST_GROUPS];
     st.uops = acc[ST_UOPS];
+    st.near_ties = acc[ST_NEARTIES];
     st.exec_launches = exec_launches;
     b->have_results = true;
     b->have_dump = b->dump_shot >= 0;
@@ -1317,6 +1359,16 @@ sv_status sv_get_memory(sv_batch *b, uint64_t *out, size_t n)
     if (!b->have_results) return fail(SV_ESTATE, "no results: run a circuit first");
     if (n != (size_t)b->shots) return fail(SV_EINVAL, "n=%zu, shots=%lld", n, (long long)b->shots);
     HIPCHK(hipMemcpyAsync(out, b->arena + b->lay.memory, n * 8, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return SV_OK;
+}
+
+sv_status sv_get_margins(sv_batch *b, double *out, size_t n)
+{
+    if (!b || !out) return fail(SV_EINVAL, "NULL argument");
+    if (!b->have_results) return fail(SV_ESTATE, "no results: run a circuit first");
+    if (n != (size_t)b->shots) return fail(SV_EINVAL, "n=%zu, shots=%lld", n, (long long)b->shots);
+    HIPCHK(hipMemcpyAsync(out, b->arena + b->lay.margins, n * 8, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     return SV_OK;
 }

@@ -16,7 +16,7 @@ def say(*a):
 
 
 def gpu_run(circ, noise, shots, dtype="c128", mode="batch", seed=0,
-            dump_shot=None, **opts):
+            dump_shot=None, want_margins=False, **opts):
     opts.setdefault("spin_limit_ms", SPIN_MS)
     if dump_shot is not None:
         opts["dump_shot"] = dump_shot
@@ -27,9 +27,10 @@ def gpu_run(circ, noise, shots, dtype="c128", mode="batch", seed=0,
         st = sim.stats()
         counts = sim.counts()
         state = sim.state() if dump_shot is not None else None
+        margins = sim.margins() if want_margins else None
     finally:
         sim.close()
-    return {"memory": mem, "stats": st, "counts": counts, "state": state}
+    return {"memory": mem, "stats": st, "counts": counts, "state": state, "margins": margins}
 
 
 def oracle_memory(circ, noise, shots, seed=0):

@@ -89,10 +89,13 @@ def test_invalid_noise_is_rejected():
     with pytest.raises(S.SvError) as e:
         _run_unattached(circ, bad_k)
     assert e.value.status == 1
+    # a rule attaches only to gates of its own width: a 2-qubit channel on a
+    # 1-qubit gate kind adds nothing, and the circuit is valid (it then
+    # needs an arena, SV_ESTATE)
     wrong_width = W.noise_model([W.rule(["h"], W.depolarizing_pauli(0.1, 2))])
     with pytest.raises(S.SvError) as e:
         _run_unattached(circ, wrong_width)
-    assert e.value.status == 1
+    assert e.value.status == 4
 
 
 def test_valid_circuit_needs_arena():

@@ -35,6 +35,112 @@ def test_small_random_circuits_c128_exact(n):
     assert mismatches(got["memory"], exp) == 0
 
 
+@pytest.mark.parametrize("mode,n,tile", [("batch", 6, 0), ("branch", 6, 0), ("plain", 6, 0),
+                                         ("batch", 14, 12), ("branch", 14, 12)])
+def test_decision_margins_match_oracle(mode, n, tile):
+    # measurement-only decisions (Pauli noise, mid-circuit measures, final
+    # sampling): both sides take the same choices from the same running
+    # sums, so the smallest margin of every shot agrees to rounding
+    circ = W.random_small(n, 60, seed=20 + n, n_mid=4)
+    noise = W.noise_model([W.rule(["u3", "h"], W.depolarizing_pauli(0.05, 1)),
+                           W.rule(["cx", "cz", "swap", "unitary"], W.depolarizing_pauli(0.05, 2))])
+    shots = 200 if mode != "plain" else 24
+    opts = {"tile_qubits": tile} if tile else {}
+    say(f"case margins mode={mode} n={n} tile={tile}")
+    got = gpu_run(circ, noise, shots, dtype="c128", mode=mode, seed=13, want_margins=True, **opts)
+    exp, marg = oracle.run(circ, noise, shots, seed=13, want_margins=True)
+    assert mismatches(got["memory"], exp) == 0
+    assert np.allclose(got["margins"], marg, rtol=1e-9, atol=1e-13)
+    assert got["stats"]["near_ties"] == int(np.sum(got["margins"] < 1e-9))
+
+
+@pytest.mark.parametrize("mode,n,tile", [("batch", 5, 0), ("branch", 14, 12)])
+def test_one_qubit_rule_on_mixed_width_unitaries(mode, n, tile):
+    # a one-qubit Kraus channel on the "unitary" kind attaches after the
+    # one-qubit unitaries only, as the oracle expands it
+    rng = np.random.default_rng(4)
+
+    def haar(d):
+        z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+        q, r = np.linalg.qr(z)
+        return (q * (np.diag(r) / abs(np.diag(r)))).tolist()
+
+    ops = []
+    for _ in range(12):
+        a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+        ops.append({"kind": "unitary", "qubits": [a], "matrix": haar(2)})
+        ops.append({"kind": "unitary", "qubits": [a, b], "matrix": haar(4)})
+    ops.append({"kind": "measure", "qubits": list(range(n)), "clbits": list(range(n))})
+    circ = {"n_qubits": n, "n_clbits": n, "ops": ops}
+    noise = W.noise_model([W.rule(["unitary"], W.amplitude_damping_kraus(0.2))])
+    opts = {"tile_qubits": tile} if tile else {}
+    say(f"case mixed-width unitary rule mode={mode} n={n}")
+    got = gpu_run(circ, noise, 128, dtype="c128", mode=mode, seed=5, **opts)
+    assert mismatches(got["memory"], oracle_memory(circ, noise, 128, seed=5)) == 0
+
+
+def _dense_noise():
+    # rules attach by width: a random 3-qubit Kraus channel (4 matrices)
+    # and a random 3-qubit Pauli channel (64 terms) after the 3-qubit
+    # unitaries, a random 4-qubit Kraus channel (3 matrices) after the
+    # 4-qubit ones, a random 5-qubit Pauli channel (1024 terms) after the
+    # 5-qubit ones
+    return W.noise_model(
+        [W.rule(["u3"], W.amplitude_damping_kraus(0.05)),
+         W.rule(["unitary"], W.random_kraus(3, 4, seed=1)),
+         W.rule(["unitary"], W.random_pauli_channel(3, seed=2, p_noise=0.3)),
+         W.rule(["unitary"], W.random_kraus(4, 3, seed=3)),
+         W.rule(["unitary"], W.random_pauli_channel(5, seed=4, p_noise=0.3)),
+         W.rule(["cx"], W.depolarizing_pauli(0.05, 2))],
+        readout=(0.01, 0.02))
+
+
+@pytest.mark.parametrize("mode,n,tile", [("batch", 6, 0), ("branch", 6, 0), ("plain", 7, 0),
+                                         ("batch", 15, 12), ("branch", 15, 12),
+                                         ("batch", 15, 13), ("branch", 16, 13)])
+def test_dense_multi_qubit_ops_match_oracle(mode, n, tile):
+    # dense unitaries on 3, 4 and 5 qubits with multi-qubit Kraus and Pauli
+    # channels, mid-circuit measures; complex128, resident (n <= tile) and
+    # streamed tiles (dense ops as LDS sweeps, 3-qubit Pauli strings fused
+    # into register groups, the 5-qubit ones as LDS sweeps when they exceed
+    # the group width); branch mode splits 1024-term Pauli draws by rank
+    circ = W.random_dense(n, 30, seed=30 + n + tile, n_mid=2)
+    noise = _dense_noise()
+    shots = 128 if mode != "plain" else 16
+    opts = {"tile_qubits": tile} if tile else {}
+    say(f"case dense multi-qubit ops mode={mode} n={n} tile={tile}")
+    got = gpu_run(circ, noise, shots, dtype="c128", mode=mode, seed=9, **opts)
+    exp = oracle_memory(circ, noise, shots, seed=9)
+    assert mismatches(got["memory"], exp) == 0
+    if mode == "branch":
+        assert got["stats"]["branches"] >= 1
+
+
+def test_dense_multi_qubit_ops_complex64():
+    circ = W.random_dense(15, 30, seed=61, n_mid=2)
+    noise = _dense_noise()
+    say("case dense multi-qubit ops c64 n=15 tile 13")
+    got = gpu_run(circ, noise, 256, dtype="c64", seed=9, tile_qubits=13)
+    exp = oracle_memory(circ, noise, 256, seed=9)
+    assert mismatches(got["memory"], exp) <= 3
+
+
+def test_op_wider_than_the_tile_is_refused():
+    # a 5-qubit unitary on high qubits with qubits 0..3 needs 9 tile qubits
+    import paper_2308_03399_amd as S
+    rng = np.random.default_rng(0)
+    circ = {"n_qubits": 12, "n_clbits": 0,
+            "ops": [{"kind": "unitary", "qubits": [7, 8, 9, 10, 11],
+                     "matrix": W.haar_unitary(32, rng).tolist()}]}
+    sim = S.Simulator(12, 4, dtype="c64", tile_qubits=8)
+    try:
+        with pytest.raises(S.SvError) as e:
+            sim.run(circ, None, seed=0)
+        assert e.value.status == 5  # SV_EUNSUPPORTED
+    finally:
+        sim.close()
+
+
 def test_c1_workload_exact():
     w = W.workload("c1_10q")
     say("case c1 10q x 20 layers, 1000 shots, c128 batch")

@@ -166,6 +166,41 @@ def test_kraus_choice_follows_running_sum():
         assert mem[s] == exp, s
 
 
+def test_decision_margin_closed_forms():
+    # margin = distance from u*N to the nearest running-sum boundary of the
+    # chosen candidate, over N. Bell measure: boundary 1/2, margin |u - 1/2|.
+    # Amplitude damping on |+>: boundary p0 = 1 - g/2; the following measure
+    # of the damped state has boundary 1/(2 - g) (K0) or none (K1: |0>, the
+    # first outcome is certain and its upper boundary C_0 = N sits at the
+    # top of the range). A circuit without Kraus or measure choices: +inf.
+    bell = {"n_qubits": 2, "n_clbits": 2,
+            "ops": [{"kind": "h", "qubits": [0]}, {"kind": "cx", "qubits": [0, 1]},
+                    {"kind": "measure", "qubits": [0, 1], "clbits": [0, 1]}]}
+    _, marg = oracle.run(bell, None, 500, seed=9, want_margins=True)
+    for s in range(500):
+        u = oracle.uniform(9, s, 2, 0)
+        assert marg[s] == pytest.approx(abs(u - 0.5), abs=1e-15), s
+    g = 0.3
+    noise = W.noise_model([W.rule(["h"], W.amplitude_damping_kraus(g))])
+    circ = {"n_qubits": 1, "n_clbits": 1,
+            "ops": [{"kind": "h", "qubits": [0]},
+                    {"kind": "measure", "qubits": [0], "clbits": [0]}]}
+    _, marg = oracle.run(circ, noise, 500, seed=2, want_margins=True)
+    for s in range(500):
+        uk = oracle.uniform(2, s, 1, 0)
+        um = oracle.uniform(2, s, 2, 0)
+        mk = abs(uk - (1 - g / 2))
+        if uk >= 1 - g / 2:          # K1: |0>, measure margin 1 - um (boundary C_0 = N)
+            exp = min(mk, 1 - um)
+        else:
+            exp = min(mk, abs(um - 1 / (2 - g)))
+        assert marg[s] == pytest.approx(exp, abs=1e-14), s
+    free = {"n_qubits": 2, "n_clbits": 0, "ops": [{"kind": "h", "qubits": [0]}]}
+    _, marg = oracle.run(free, W.depol_model(0.5, 0.5, gates1=("h",)), 4, seed=1,
+                         want_margins=True)
+    assert np.all(np.isinf(marg))
+
+
 def test_readout_flip_draw():
     circ = {"n_qubits": 1, "n_clbits": 1,
             "ops": [{"kind": "measure", "qubits": [0], "clbits": [0]}]}
@@ -425,3 +460,41 @@ def test_conditionals_dm_equals_tree_and_oracle_samples(seed):
     shots = 30000
     mem = oracle.run(circ, noise, shots, seed=17 + seed)
     _sample_check(mem, d, shots)
+
+
+def test_multi_qubit_channels_dm_equals_tree_and_oracle():
+    # dense 3-qubit unitaries followed by a random 3-qubit Kraus channel (4
+    # matrices, not diagonal) and a random 3-qubit Pauli channel (64
+    # terms): the exact register distribution by density matrices equals
+    # the trajectory-tree enumeration, and oracle samples follow it
+    rng = np.random.default_rng(5)
+    ops = [{"kind": "h", "qubits": [0]}, {"kind": "cx", "qubits": [0, 3]}]
+    for qs in ([0, 1, 2], [3, 1, 0]):
+        ops.append({"kind": "unitary", "qubits": qs,
+                    "matrix": W.haar_unitary(8, rng).tolist()})
+    ops.append({"kind": "measure", "qubits": [0, 1, 2, 3], "clbits": [0, 1, 2, 3]})
+    circ = {"n_qubits": 4, "n_clbits": 4, "ops": ops}
+    noise = W.noise_model([W.rule(["unitary"], W.random_kraus(3, 4, seed=1)),
+                           W.rule(["unitary"], W.random_pauli_channel(3, seed=2, p_noise=0.4))],
+                          readout=(0.01, 0.02))
+    d = dm.creg_distribution_dm(circ, noise)
+    t = dm.creg_distribution_tree(circ, noise)
+    assert abs(sum(d.values()) - 1) < 1e-12
+    assert dm.tvd(d, t) < 1e-12
+    mem = oracle.run(circ, noise, 30000, seed=3)
+    _sample_check(mem, d, 30000)
+
+
+@pytest.mark.parametrize("w", [3, 4, 5])
+def test_dense_unitary_round_trip(w):
+    # U then U^dagger on w qubits returns |0..0> up to rounding
+    rng = np.random.default_rng(w)
+    u = W.haar_unitary(1 << w, rng)
+    qs = [int(x) for x in rng.choice(6, w, replace=False)]
+    circ = {"n_qubits": 6, "n_clbits": 0,
+            "ops": [{"kind": "h", "qubits": [q]} for q in range(6)] +
+                   [{"kind": "unitary", "qubits": qs, "matrix": u.tolist()},
+                    {"kind": "unitary", "qubits": qs, "matrix": u.conj().T.tolist()}] +
+                   [{"kind": "h", "qubits": [q]} for q in range(6)]}
+    _, psi = oracle.run(circ, None, [0], want_state=True)
+    assert abs(psi[0] - 1) < 1e-13 and np.max(np.abs(psi[1:])) < 1e-13

@@ -98,3 +98,24 @@ def test_plan_reorders_to_fewer_passes_than_list_order():
     order, opass, _, _, _ = _plan(w["circuit"], w["noise"], 13, 5)
     layers = 60
     assert opass.max() + 1 < 3 * layers  # list-order planning needs about 3 per layer
+
+
+def test_rule_attaches_only_to_gates_of_its_width():
+    # a one-qubit channel on the "unitary" kind: expanded after the 1-qubit
+    # unitaries only, as the oracle expands it (the plan holds every
+    # expanded op once)
+    rng = np.random.default_rng(3)
+
+    def haar(d):
+        z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+        q, r = np.linalg.qr(z)
+        return q * (np.diag(r) / abs(np.diag(r)))
+
+    ops = [{"kind": "unitary", "qubits": [0], "matrix": haar(2)},
+           {"kind": "unitary", "qubits": [1, 2], "matrix": haar(4)},
+           {"kind": "unitary", "qubits": [2], "matrix": haar(2)},
+           {"kind": "measure", "qubits": [0, 1, 2], "clbits": [0, 1, 2]}]
+    circ = {"n_qubits": 3, "n_clbits": 3, "ops": ops}
+    noise = W.noise_model([W.rule(["unitary"], W.amplitude_damping_kraus(0.2))])
+    order, _, _, _, _ = _plan(circ, noise, 3, 0)
+    assert sorted(order.tolist()) == list(range(6))  # 4 ops + 2 channels

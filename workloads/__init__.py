@@ -72,6 +72,67 @@ def depolarizing_pauli(p: float, nq: int) -> Dict:
     return {"type": "pauli", "nq": nq, "probs": probs, "paulis": paulis}
 
 
+def haar_unitary(dim: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-random unitary (QR of a complex Gaussian matrix, phases fixed)."""
+    z = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def random_kraus(nq: int, n_mats: int, seed: int) -> Dict:
+    """Random n-qubit Kraus channel of n_mats matrices: the blocks of a
+    random isometry (QR of a (n_mats*2^nq) x 2^nq complex Gaussian), so
+    sum_j K_j^dagger K_j = I."""
+    rng = np.random.default_rng(seed)
+    d = 1 << nq
+    z = rng.normal(size=(n_mats * d, d)) + 1j * rng.normal(size=(n_mats * d, d))
+    v, _ = np.linalg.qr(z)
+    return {"type": "kraus", "nq": nq,
+            "mats": [v[j * d:(j + 1) * d, :].tolist() for j in range(n_mats)]}
+
+
+def random_pauli_channel(nq: int, seed: int, p_noise: float = 0.3) -> Dict:
+    """Random n-qubit Pauli channel over all 4^nq strings (base-4 order as
+    in depolarizing_pauli): identity 1 - p_noise, the rest split by random
+    weights."""
+    rng = np.random.default_rng(seed)
+    base = depolarizing_pauli(0.0, nq)
+    w = rng.random(4 ** nq - 1)
+    probs = [1.0 - p_noise] + list(p_noise * w / w.sum())
+    return {"type": "pauli", "nq": nq, "probs": probs, "paulis": base["paulis"]}
+
+
+def random_dense(n_qubits: int, n_ops: int, seed: int, widths=(3, 4, 5),
+                 n_mid: int = 0) -> Dict:
+    """Random circuit of dense unitaries on `widths` qubits mixed with U3
+    and CX gates, optional mid-circuit measures, final measure of all
+    qubits."""
+    rng = np.random.default_rng(seed)
+    ops: List[Dict] = []
+    n_cl = n_qubits
+    mid_at = set(rng.choice(n_ops, size=min(n_mid, n_ops), replace=False).tolist()) if n_mid else set()
+    for i in range(n_ops):
+        k = int(rng.integers(3))
+        if k == 0:
+            w = int(rng.choice([x for x in widths if x <= n_qubits]))
+            qs = [int(x) for x in rng.choice(n_qubits, w, replace=False)]
+            ops.append({"kind": "unitary", "qubits": qs,
+                        "matrix": haar_unitary(1 << w, rng).tolist()})
+        elif k == 1:
+            ops.append({"kind": "u3", "qubits": [int(rng.integers(n_qubits))],
+                        "params": [float(x) for x in rng.uniform(0, 2 * math.pi, 3)]})
+        else:
+            a, b = (int(x) for x in rng.choice(n_qubits, 2, replace=False))
+            ops.append({"kind": "cx", "qubits": [a, b]})
+        if i in mid_at:
+            q = int(rng.integers(n_qubits))
+            ops.append({"kind": "measure", "qubits": [q], "clbits": [n_cl]})
+            n_cl += 1
+    ops.append({"kind": "measure", "qubits": list(range(n_qubits)),
+                "clbits": list(range(n_qubits))})
+    return {"n_qubits": n_qubits, "n_clbits": n_cl, "ops": ops}
+
+
 def pauli_table(probs: Sequence[float], paulis: Sequence[str]) -> Dict:
     nq = len(paulis[0])
     return {"type": "pauli", "nq": nq, "probs": list(map(float, probs)),
