@@ -42,7 +42,7 @@ import numpy as np
 from . import (SV_C128, SV_C64, SV_MODE_BATCH, SV_MODE_BRANCH, marshal,
                sv_batch_attach, sv_batch_create, sv_batch_destroy,
                sv_batch_footprint, sv_batch_set_option, sv_get_memory,
-               sv_run_circuit)
+               sv_run_circuit, sv_sample_counts)
 
 MODES = {"batch": SV_MODE_BATCH, "branch": SV_MODE_BRANCH}
 GATE_KINDS = ("u3", "h", "x", "y", "z", "s", "sdg", "t", "tdg", "id",
@@ -173,7 +173,9 @@ class DeviceBackend:
             sv_batch_destroy(h)
 
     def run(self, req: Request, prepared, offset: int, n_shots: int, workers: int,
-            arena_bytes: int, stream) -> np.ndarray:
+            arena_bytes: int, stream):
+        """One chunk: per-shot registers and the chunk's histogram (the
+        library's device sort and run-length encoding)."""
         torch = self.torch
         h = self._handle(req, n_shots, workers, offset)
         try:
@@ -183,8 +185,9 @@ class DeviceBackend:
                 # synchronous on `stream`: returns when the launch has finished
                 sv_run_circuit(h, prepared, req.seed)
                 mem = sv_get_memory(h, n_shots)
+                counts = sv_sample_counts(h, capacity=n_shots)
                 del arena
-            return mem
+            return mem, counts
         finally:
             sv_batch_destroy(h)
 
@@ -320,6 +323,7 @@ class Server:
         gates = count_gates(req.circuit)
         prepared = self.backend.prepare(req)
         mem = np.empty(req.shots, dtype=np.uint64)
+        counts: collections.Counter = collections.Counter()
         chunks: List[Chunk] = []
         # ms of one wave (one shot per workgroup); refined from measurements
         wave_ms = MS_PER_AMP_GATE * max(1 << n, MIN_AMPS) * max(gates, 1)
@@ -336,17 +340,18 @@ class Server:
                 t0 = time.perf_counter()
                 if t_start is None:
                     t_start = t0
-                mem[offset:offset + c] = self.backend.run(req, prepared, offset, c, w,
-                                                          nbytes, stream)
+                mem[offset:offset + c], part = self.backend.run(req, prepared, offset, c, w,
+                                                                nbytes, stream)
+                counts.update(part)
                 t1 = time.perf_counter()
             finally:
                 self._release(nbytes)
             chunks.append(Chunk(offset, c, w, nbytes, t0, t1))
             wave_ms = 1e3 * (t1 - t0) / math.ceil(c / w)
             offset += c
-        keys, cnt = np.unique(mem, return_counts=True)
+        # chunks cover disjoint shot ranges: their histograms add up
         return Result(id=req.id, memory=mem,
-                      counts={int(k): int(v) for k, v in zip(keys, cnt)},
+                      counts={k: counts[k] for k in sorted(counts)},
                       gates=gates, shots=req.shots, n_qubits=n, t_submit=ticket.t_submit,
                       t_start=t_start, t_done=time.perf_counter(), chunks=chunks)
 

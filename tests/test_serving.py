@@ -56,7 +56,9 @@ class FakeBackend:
         with self.lock:
             self.live_bytes -= arena_bytes
             self.live_chunks -= 1
-        return _expected(req.seed, offset, offset + n_shots)
+        mem = _expected(req.seed, offset, offset + n_shots)
+        keys, cnt = np.unique(mem, return_counts=True)
+        return mem, {int(k): int(c) for k, c in zip(keys, cnt)}
 
 
 def _req(i, shots, n=10, seed=None):
@@ -80,7 +82,10 @@ def test_chunks_cover_every_shot_once():
             assert c.offset == pos and c.shots >= 1
             pos += c.shots
         assert pos == r.shots
-        assert sum(res.counts.values()) == r.shots
+        # the merged chunk histograms are the histogram of the whole request
+        keys, cnt = np.unique(res.memory, return_counts=True)
+        assert res.counts == {int(k): int(c) for k, c in zip(keys, cnt)}
+        assert list(res.counts) == sorted(res.counts)
         assert res.gates == 5
         assert res.t_submit <= res.t_start <= res.t_done
     # the 300-shot request ran in several chunks (measured wave time)
