@@ -713,6 +713,61 @@ __device__ __forceinline__ void d_mat1(A (&v)[NR], int j, const R (&m)[8], int k
 #undef SVB_M1
 }
 
+// complex64 one-qubit micro-op on the matrix cores. A 2x2 complex matrix
+// acting on an amplitude pair (a, b) is the real 4x4 matrix M acting on
+// x = (re a, im a, re b, im b). v_mfma_f32_4x4x1f32 (16 blocks of 4 lanes)
+// computes, in lane l and result register i, sum over its K = 1 of
+// A(lane 4*(l/4) + i) * B(lane l). With lane l holding row l%4 of column k
+// of M in A and component k of its own pair in B, four accumulating
+// instructions give each lane M x for its pair: the same 16 products per
+// pair as the vector form, at twice its rate and off the vector ALU.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int J, int NR>
+__device__ __forceinline__ void r_mat1_mfma(f32x2 (&v)[NR], const float (&a)[4])
+{
+    if constexpr ((1 << J) < NR) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (i & (1 << J)) continue;
+            const int i1 = i | (1 << J);
+            f32x4 d = {0.f, 0.f, 0.f, 0.f};
+            d = __builtin_amdgcn_mfma_f32_4x4x1f32(a[0], v[i].x, d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_4x4x1f32(a[1], v[i].y, d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_4x4x1f32(a[2], v[i1].x, d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_4x4x1f32(a[3], v[i1].y, d, 0, 0, 0);
+            v[i].x = d[0];
+            v[i].y = d[1];
+            v[i1].x = d[2];
+            v[i1].y = d[3];
+        }
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ void d_mat1_mfma(f32x2 (&v)[NR], int j, const float (&a)[4])
+{
+#define SVB_M1(J) case J: r_mat1_mfma<J, NR>(v, a); break;
+    switch (j) { SVB_M1(0) SVB_M1(1) SVB_M1(2) SVB_M1(3) SVB_M1(4) SVB_M1(5) default: break; }
+#undef SVB_M1
+}
+
+// This lane's entries of the real 4x4 form of the fused matrix m (row-major
+// 2x2 complex, interleaved re/im): row r = lane % 4 of columns 0..3.
+//   r = 0: ( re m00, -im m00,  re m01, -im m01)    (re of output a)
+//   r = 1: ( im m00,  re m00,  im m01,  re m01)    (im of output a)
+//   r = 2, 3: the same with m10, m11               (output b)
+__device__ __forceinline__ void mfma_rows(const lds<float> *m, uint32_t lane, float (&a)[4])
+{
+    const uint32_t r = lane & 3u;
+    const f32x4 x = *(const lds<f32x4> *)(m + (r >> 1) * 4);
+    const bool odd = (r & 1u) != 0;
+    a[0] = odd ? x.y : x.x;
+    a[1] = odd ? x.x : -x.y;
+    a[2] = odd ? x.w : x.z;
+    a[3] = odd ? x.z : -x.w;
+}
+
 template <class A, int NR>
 __device__ __forceinline__ void d_two(A (&v)[NR], int kind, int c, int t)
 {
@@ -790,10 +845,16 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
     for (int q = 0; q < count; ++q) {
         const UOp u = get_uop(uops + first + q);
         if (u.kind == UK_MAT1 || u.kind == UK_DIAG1 || u.kind == UK_MAT1R) {
-            R m[8];
+            if constexpr (sizeof(R) == 4) {
+                float a4[4];
+                mfma_rows(mats + u.mat * 8, (uint32_t)h.tid, a4);
+                d_mat1_mfma<NR>(v, u.j0, a4);
+            } else {
+                R m[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) m[e] = uni(mats[u.mat * 8 + e]);
-            d_mat1<A, R, NR>(v, u.j0, m, u.kind);
+                for (int e = 0; e < 8; ++e) m[e] = uni(mats[u.mat * 8 + e]);
+                d_mat1<A, R, NR>(v, u.j0, m, u.kind);
+            }
         } else {
             d_two<A, NR>(v, u.kind, u.j0, u.j1);
         }
