@@ -243,6 +243,28 @@ sv_status sv_run_sweep(sv_batch *b, const sv_op *ops, size_t n_ops,
                        const sv_noise_model *nm, uint64_t seed,
                        const double *params, size_t n_sets);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The run of
+ * sv_run_circuit, with the same results, on a device buffer the library
+ * owns instead of an attached arena: a file-scope array of
+ * SV_NOALLOC_MAX_BYTES on every GPU the library runs on, held from module
+ * load until the process ends. The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine). b must not be attached
+ * (SV_ESTATE); the work is enqueued on hip_stream (NULL: the null stream)
+ * and the call blocks until it is done, then writes the n_memory == n_shots
+ * per-shot registers to memory_out (host). The state slots are fitted to
+ * the buffer (batch mode: as many workgroups as states fit); a run that
+ * does not fit with one state slot fails with SV_ENOMEM and a message
+ * giving the bytes it needs. Only sv_get_stats stays valid afterwards:
+ * counts, margins and state dumps are not kept. Every call on one GPU
+ * shares that GPU's buffer: calls that overlap on one GPU (other threads,
+ * other handles) race and must be serialised by the caller. */
+#define SV_NOALLOC_MAX_BYTES (64ull << 20)
+sv_status sv_run_circuit_noalloc(sv_batch *b, const sv_op *ops, size_t n_ops,
+                                 const sv_noise_model *nm, uint64_t seed,
+                                 void *hip_stream, uint64_t *memory_out,
+                                 size_t n_memory);
+
 /* Bit-count histogram of the last run (Sec. III-B): keys[i] is a classical
  * register value (clbit c <-> bit c), counts[i] its number of shots, keys
  * ascending. If capacity < the number of distinct keys, *n_unique receives

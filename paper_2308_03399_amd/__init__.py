@@ -30,7 +30,8 @@ PAULI_CODE = {"I": 0, "X": 1, "Y": 2, "Z": 3}
 MAX_INLINE = 8
 
 EXPORTED = ["sv_batch_create", "sv_batch_footprint", "sv_batch_attach",
-            "sv_batch_set_option", "sv_run_circuit", "sv_run_sweep", "sv_sample_counts",
+            "sv_batch_set_option", "sv_run_circuit", "sv_run_sweep",
+            "sv_run_circuit_noalloc", "sv_sample_counts",
             "sv_get_memory", "sv_get_margins", "sv_get_state", "sv_get_stats",
             "sv_batch_destroy", "sv_last_error"]
 
@@ -118,6 +119,9 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(sv_noise_model), U64]
     L.sv_run_sweep.argtypes = [P, ctypes.POINTER(sv_op), ctypes.c_size_t,
                                ctypes.POINTER(sv_noise_model), U64, P, ctypes.c_size_t]
+    L.sv_run_circuit_noalloc.argtypes = [P, ctypes.POINTER(sv_op), ctypes.c_size_t,
+                                         ctypes.POINTER(sv_noise_model), U64, P, P,
+                                         ctypes.c_size_t]
     L.sv_sample_counts.argtypes = [P, P, P, ctypes.c_size_t,
                                    ctypes.POINTER(ctypes.c_size_t)]
     L.sv_get_memory.argtypes = [P, P, ctypes.c_size_t]
@@ -173,6 +177,17 @@ def sv_run_sweep(h: int, marshalled, seed: int, params) -> None:
     if a.ndim != 3 or a.shape[2] != 3:
         raise ValueError("params must have shape (n_sets, n_u3, 3)")
     _check(lib().sv_run_sweep(h, ops, n_ops, nm, int(seed), a.ctypes.data, a.shape[0]))
+
+
+def sv_run_circuit_noalloc(h: int, marshalled, seed: int, stream: int,
+                           n_shots: int) -> np.ndarray:
+    """The run of sv_run_circuit on the library's own device buffer (the
+    handle is not attached); returns the per-shot registers."""
+    ops, n_ops, nm = marshalled["ops"], marshalled["n_ops"], marshalled["nm"]
+    out = np.zeros(n_shots, dtype=np.uint64)
+    _check(lib().sv_run_circuit_noalloc(h, ops, n_ops, nm, int(seed), stream,
+                                        out.ctypes.data, n_shots))
+    return out
 
 
 def sv_sample_counts(h: int, capacity: int = 0) -> Dict[int, int]:

@@ -14,7 +14,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libsvbatch.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["runtime.cpp", "kernels.hip", "counts.hip", "plain.hip"]
+SOURCES = ["runtime.cpp", "kernels.hip", "counts.hip", "plain.hip", "noalloc.hip"]
 ARCH = os.environ.get("SVB_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed-FP32 instructions in device code

@@ -36,6 +36,7 @@ hipError_t svb_counts(const uint64_t *memory, int64_t n, void *temp, size_t temp
                       uint64_t *keys_sorted, uint64_t *uniq, uint32_t *cnt, uint32_t *n_uniq,
                       hipStream_t st);
 size_t svb_counts_temp_bytes(int64_t n);
+hipError_t svb_noalloc_scratch(void **ptr, uint64_t *bytes);
 hipError_t svb_plain_run(int is_c128, const DevOp *ops, const DevOp *hops, int n_ops,
                          const DevRule *rules, const DevRule *hrules, const double *pool, int n,
                          uint64_t n_shots, uint64_t shot_base, uint64_t seed, void *state,
@@ -104,7 +105,6 @@ struct sv_batch {
     int64_t wallclock_khz = 100000;
     int64_t auto_slots = 0;            // branch mode's automatic slot count, fixed at first sizing
     int64_t auto_workers = 0;          // batch mode's memory-bounded worker count, same
-    uint64_t arena_cap = 0;            // >0: workers and slots are fitted to an arena this size
     bool no_counts = false;            // no room reserved for the counts histogram
     // arena
     bool attached = false;
@@ -117,6 +117,7 @@ struct sv_batch {
     } lay{};
     // results
     bool have_results = false;
+    bool have_stats = false;
     bool have_dump = false;
     sv_stats stats{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
@@ -973,6 +974,7 @@ static sv_status run_empty(sv_batch *b)
     st.tile_qubits = (uint32_t)b->tile_q;
     st.tile_buffers = (uint32_t)b->nbuf;
     b->have_results = true;
+    b->have_stats = true;
     b->have_dump = b->dump_shot >= 0;
     return SV_OK;
 }
@@ -990,6 +992,7 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
         if ((uint64_t)b->shots / n_sets > 0xffffffffull) return fail(SV_EINVAL, "too many shots per set");
     }
     b->have_results = false;
+    b->have_stats = false;
     b->have_dump = false;
     std::vector<Rule> rules;
     std::vector<XOp> xo;
@@ -1250,6 +1253,7 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
         st.passes = (uint64_t)b->shots * (rw + ro);
         st.amp_bytes = (uint64_t)b->shots * (2 * rw + ro) * state_bytes(b);
         b->have_results = true;
+        b->have_stats = true;
         b->have_dump = false;
         return SV_OK;
     }
@@ -1309,6 +1313,7 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     st.near_ties = acc[ST_NEARTIES];
     st.exec_launches = exec_launches;
     b->have_results = true;
+    b->have_stats = true;
     b->have_dump = b->dump_shot >= 0;
     return SV_OK;
 }
@@ -1324,6 +1329,67 @@ sv_status sv_run_sweep(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_noi
 {
     if (!params) return fail(SV_EINVAL, "params is NULL");
     return run_impl(b, ops, n_ops, nm, seed, params, n_sets);
+}
+
+// Fit the state slots (and in batch mode the workgroups that own them, one
+// slot each) into an arena of cap bytes; the rest of the layout is fixed by
+// the shot count and the options.
+static sv_status fit_arena(sv_batch *b, uint64_t cap)
+{
+    layout(b);
+    while (b->lay.total > cap && b->slots > 1) {
+        const uint64_t over = b->lay.total - cap;
+        const int64_t drop = std::max<int64_t>(1, (int64_t)((over + state_bytes(b) - 1) / state_bytes(b)));
+        b->slots = (int)std::max<int64_t>(1, (int64_t)b->slots - drop);
+        if (b->mode == SV_MODE_BATCH && !b->resident) b->workers = b->slots;
+        layout(b);
+    }
+    if (b->lay.total > cap)
+        return fail(SV_ENOMEM, "needs %llu device bytes with one state slot, more than the "
+                    "%llu of the no-allocation buffer (fewer shots or a smaller program_bytes "
+                    "may fit)", (unsigned long long)b->lay.total, (unsigned long long)cap);
+    return SV_OK;
+}
+
+sv_status sv_run_circuit_noalloc(sv_batch *b, const sv_op *ops, size_t n_ops,
+                                 const sv_noise_model *nm, uint64_t seed, void *hip_stream,
+                                 uint64_t *memory_out, size_t n_memory)
+{
+    if (!b || !memory_out) return fail(SV_EINVAL, "NULL argument");
+    if (b->attached) return fail(SV_ESTATE, "the handle has an attached arena: use sv_run_circuit");
+    if (n_memory != (size_t)b->shots)
+        return fail(SV_EINVAL, "n_memory=%zu, shots=%lld", n_memory, (long long)b->shots);
+    void *ptr = nullptr;
+    uint64_t cap = 0;
+    HIPCHK(svb_noalloc_scratch(&ptr, &cap));
+    b->no_counts = true;
+    sv_status s = derive(b);
+    if (s == SV_OK) s = fit_arena(b, cap);
+    if (s == SV_OK) {
+        b->arena = (char *)ptr;
+        b->arena_bytes = cap;
+        b->stream = (hipStream_t)hip_stream;
+        b->attached = true;
+        s = run_impl(b, ops, n_ops, nm, seed, nullptr, 1);
+        if (s == SV_OK) {
+            const hipError_t e1 = hipMemcpyAsync(memory_out, b->arena + b->lay.memory, n_memory * 8,
+                                                 hipMemcpyDeviceToHost, b->stream);
+            const hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(b->stream) : e1;
+            if (e2 != hipSuccess)
+                s = fail(SV_EDEVICE, "copy of the registers: %s", hipGetErrorString(e2));
+        }
+    }
+    // every no-allocation call on this device shares the buffer: nothing of
+    // this run stays readable through the handle but its statistics
+    b->attached = false;
+    b->arena = nullptr;
+    b->arena_bytes = 0;
+    b->stream = nullptr;
+    b->no_counts = false;
+    b->have_results = false;
+    b->have_dump = false;
+    if (s != SV_OK) b->have_stats = false;
+    return s;
 }
 
 sv_status sv_sample_counts(sv_batch *b, uint64_t *keys, uint64_t *counts, size_t capacity,
@@ -1386,7 +1452,7 @@ sv_status sv_get_state(sv_batch *b, double *amps, size_t n_amps)
 sv_status sv_get_stats(sv_batch *b, sv_stats *out)
 {
     if (!b || !out) return fail(SV_EINVAL, "NULL argument");
-    if (!b->have_results) return fail(SV_ESTATE, "no results: run a circuit first");
+    if (!b->have_stats) return fail(SV_ESTATE, "no results: run a circuit first");
     *out = b->stats;
     return SV_OK;
 }
