@@ -50,6 +50,11 @@ FP32_VECTOR_PEAK_TF = 157.3    # MI355X published FP32 vector
 FP64_VECTOR_PEAK_TF = 78.6
 
 
+def progress(msg: str):
+    """One progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     """Hash of the executor's source and of the build script (its flags)."""
     h = hashlib.sha256()
@@ -177,6 +182,8 @@ def c64_vs_fp64(mem64, mem128, circ, noise, seed, n_state_shots=64):
     tvds, errs, infid = [], [], []
     for k in range(n_state_shots):
         shot = k * (B // n_state_shots)
+        if k % 8 == 0:
+            progress(f"final states of shot {shot} ({k + 1}/{n_state_shots}), complex64 and FP64")
         sa = shot_state(circ, noise, seed, "c64", shot)
         sb = shot_state(circ, noise, seed, "c128", shot)
         pa, pb = np.abs(sa) ** 2, np.abs(sb) ** 2
@@ -480,6 +487,7 @@ def main():
     mem_first = None  # per-shot registers of shot ids 0..B-1 (untimed warm-up)
     for i in range(args.warmup):
         step(i)
+        progress(f"warm-up step {i + 1}/{args.warmup} done")
         if i == 0:
             mem_first = sim.memory()
     torch.cuda.synchronize()
@@ -489,6 +497,7 @@ def main():
         st, counts = step(i)
         assert sum(counts.values()) == B
         stats.append(st)
+        progress(f"timed step {i + 1}/{args.steps}: {st['exec_ms']:.1f} ms executor")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
@@ -550,7 +559,9 @@ def main():
     roof["copy_ceiling_gbs"] = round(copy_gbs, 1)
     roof["hbm_frac_of_copy"] = round(gbs / copy_gbs, 4)
     mem128 = None
+    progress(f"copy ceiling {copy_gbs:.0f} GB/s")
     if not args.no_c128 and args.dtype == "c64":
+        progress("complex128 wave and the complex64 comparison")
         out["c128"], mem128 = other_form(circ, noise, seed, gates, B, "c128", args.mode,
                                          keep_memory=True)
         if mem_first is not None:
@@ -558,11 +569,13 @@ def main():
     elif args.dtype == "c128":
         mem128 = mem_first
     if not args.no_branch and args.mode == "batch":
+        progress("shot-branching wave")
         br = other_form(circ, noise, seed, gates, B, args.dtype, "branch")
         br["note"] = ("shot-branching on the same shot ids: shots share a state until a "
                       "draw splits them")
         out["branch"] = br
     if args.plain_shots > 0:
+        progress("plain per-shot FP64 form")
         pl = other_form(circ, noise, seed, gates, args.plain_shots, "c128", "plain")
         pl["note"] = ("plain per-shot FP64 form: one state, one kernel per op, first "
                       f"{args.plain_shots} shot ids; time is linear in shots for this form")
@@ -570,6 +583,7 @@ def main():
         out["plain_fp64"] = pl
     if not args.no_cpu_baseline:
         import numpy as np
+        progress("FP64 oracle on the host cores")
         rec, ids, omem, omarg = cpu_baseline(circ, noise, gates, seed, w["shots"], B)
         out["cpu_baseline"] = rec
         if mem128 is not None:

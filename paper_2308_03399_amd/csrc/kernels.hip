@@ -231,22 +231,46 @@ struct WgShared {
 // UK_MAT1R: a 2x2 matrix whose top-left entry is real (a U3 gate, alone or
 // with diagonal noise factors), two multiplications fewer per pair
 enum UKind : uint8_t { UK_MAT1 = 1, UK_DIAG1 = 2, UK_CX = 3, UK_CZ = 4, UK_SWAP = 5, UK_MAT1R = 6 };
+// Dispatch code of a micro-op, one dense number per (kind, register bits)
+// so that the register-group loop branches once: one-qubit kinds on bit J
+// at kCodeMat1/kCodeMat1R/kCodeDiag1 + J, two-qubit kinds on (c, t) at
+// kCodeCX/kCodeCZ/kCodeSwap + 6c + t, and kCodeCopy (no change).
+constexpr uint32_t kCodeMat1 = 0, kCodeMat1R = 8, kCodeDiag1 = 16, kCodeCX = 24, kCodeCZ = 60,
+                   kCodeSwap = 96, kCodeCopy = 255;
 struct UOp {
-    uint8_t kind, j0, j1, pad;
+    uint8_t kind, j0, j1, code;
     uint16_t mat, pad2;
 };
+// A register group of the pass. flags bit 0: an LDS group (fallback);
+// bit 26: the group ends with a permutation of its register bits that is
+// applied by where the results are stored, not by moving them: bits
+// 1 + 5a .. 5 + 5a hold the image of register bit a (a < 5).
+constexpr uint32_t kGrpFallback = 1u, kGrpPerm = 1u << 26;
 struct UGroup {
     int32_t gidx;       // static group
     int32_t a, b;       // register group: first uop, count; LDS group: op range
-    int32_t fallback;
+    uint32_t flags;
 };
+
+__device__ __forceinline__ uint8_t uop_code(const UOp &u)
+{
+    switch (u.kind) {
+    case UK_MAT1: return (uint8_t)(kCodeMat1 + u.j0);
+    case UK_MAT1R: return (uint8_t)(kCodeMat1R + u.j0);
+    case UK_DIAG1: return (uint8_t)(kCodeDiag1 + u.j0);
+    case UK_CX: return (uint8_t)(kCodeCX + 6 * u.j0 + u.j1);
+    case UK_CZ: return (uint8_t)(kCodeCZ + 6 * u.j0 + u.j1);
+    case UK_SWAP: return (uint8_t)(kCodeSwap + 6 * u.j0 + u.j1);
+    default: return (uint8_t)kCodeCopy;
+    }
+}
 
 __device__ __forceinline__ void put_uop(lds<UOp> *p, const UOp &u)
 {
     p->kind = u.kind;
     p->j0 = u.j0;
     p->j1 = u.j1;
-    p->pad = 0;
+    p->code = uop_code(u);
     p->mat = u.mat;
     p->pad2 = 0;
 }
@@ -286,7 +310,7 @@ __device__ __forceinline__ UOp get_uop(const lds<UOp> *p)
     u.kind = (uint8_t)lo;
     u.j0 = (uint8_t)(lo >> 8);
     u.j1 = (uint8_t)(lo >> 16);
-    u.pad = 0;
+    u.code = (uint8_t)(lo >> 24);
     u.mat = (uint16_t)hi;
     u.pad2 = 0;
     return u;
@@ -300,7 +324,8 @@ __device__ __forceinline__ uint32_t svb_side_bytes_dev(int tile_q, int amp_bytes
     const uint32_t tile = (1u << tile_q) * amp_bytes * (resident ? 1u : (uint32_t)nbuf);
     const uint32_t hi = resident ? 16u : (1u << (tile_q - kCoalesceQ)) * 4u;
     const uint32_t dec = kMaxPassOps * 2;
-    const uint32_t fuse = kMaxPassGroups * 16 + kMaxPassUops * 8 + kPassMatBytes + 8 * 8 * 8;
+    const uint32_t fuse = kMaxPassGroups * (uint32_t)sizeof(UGroup) + kMaxPassUops * (uint32_t)sizeof(UOp) +
+                          kPassMatBytes + 8 * 8 * 8;
     const uint32_t cnt = 16u * kWG * 4u;
     const bool cnt_in_tile = !resident && (1u << tile_q) * amp_bytes >= cnt;
     const uint32_t ua = (!cnt_in_tile && cnt > fuse) ? cnt : fuse;
@@ -783,6 +808,153 @@ __device__ __forceinline__ void d_two(A (&v)[NR], int kind, int c, int t)
 #undef SVB_P
 }
 
+// ---- two register sets: a micro-op reads one and writes every entry of
+// the other, so a one-qubit micro-op needs no copies; the register-group
+// loop alternates between the two sets (micro-op counts are padded to even)
+template <class A, int NR>
+__device__ __forceinline__ void p_copy(const A (&v)[NR], A (&o)[NR])
+{
+#pragma unroll
+    for (int i = 0; i < NR; ++i) o[i] = v[i];
+}
+
+template <int J, class A, class R, int NR>
+__device__ __forceinline__ void p_mat1(const A (&v)[NR], A (&o)[NR], const R (&m)[8])
+{
+    if constexpr ((1 << J) < NR) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (i & (1 << J)) continue;
+            const int i1 = i | (1 << J);
+            const A a = v[i], b = v[i1];
+            A o0 = cmul<A, R>(m[0], m[1], a);
+            o0 = cmac<A, R>(o0, m[2], m[3], b);
+            A o1 = cmul<A, R>(m[4], m[5], a);
+            o1 = cmac<A, R>(o1, m[6], m[7], b);
+            o[i] = o0;
+            o[i1] = o1;
+        }
+    } else {
+        p_copy<A, NR>(v, o);
+    }
+}
+
+// real top-left entry m[0] (m[1] == 0)
+template <int J, class A, class R, int NR>
+__device__ __forceinline__ void p_mat1r(const A (&v)[NR], A (&o)[NR], const R (&m)[8])
+{
+    if constexpr ((1 << J) < NR) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (i & (1 << J)) continue;
+            const int i1 = i | (1 << J);
+            const A a = v[i], b = v[i1];
+            A o0;
+            o0.x = m[0] * a.x;
+            o0.y = m[0] * a.y;
+            o0 = cmac<A, R>(o0, m[2], m[3], b);
+            A o1 = cmul<A, R>(m[4], m[5], a);
+            o1 = cmac<A, R>(o1, m[6], m[7], b);
+            o[i] = o0;
+            o[i1] = o1;
+        }
+    } else {
+        p_copy<A, NR>(v, o);
+    }
+}
+
+template <int J, class A, class R, int NR>
+__device__ __forceinline__ void p_diag1(const A (&v)[NR], A (&o)[NR], const R (&m)[8])
+{
+    if constexpr ((1 << J) < NR) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+            o[i] = (i & (1 << J)) ? cmul<A, R>(m[6], m[7], v[i]) : cmul<A, R>(m[0], m[1], v[i]);
+    } else {
+        p_copy<A, NR>(v, o);
+    }
+}
+
+template <int C, int T, class A, int NR>
+__device__ __forceinline__ void p_cx(const A (&v)[NR], A (&o)[NR])
+{
+    if constexpr ((1 << C) < NR && (1 << T) < NR && C != T) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) o[i] = v[(i & (1 << C)) ? (i ^ (1 << T)) : i];
+    } else {
+        p_copy<A, NR>(v, o);
+    }
+}
+
+template <int C, int T, class A, int NR>
+__device__ __forceinline__ void p_cz(const A (&v)[NR], A (&o)[NR])
+{
+    if constexpr ((1 << C) < NR && (1 << T) < NR && C != T) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            o[i] = v[i];
+            if ((i & (1 << C)) && (i & (1 << T))) {
+                o[i].x = -v[i].x;
+                o[i].y = -v[i].y;
+            }
+        }
+    } else {
+        p_copy<A, NR>(v, o);
+    }
+}
+
+template <int C, int T, class A, int NR>
+__device__ __forceinline__ void p_swap(const A (&v)[NR], A (&o)[NR])
+{
+    if constexpr ((1 << C) < NR && (1 << T) < NR && C != T) {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int bc = (i >> C) & 1, bt = (i >> T) & 1;
+            o[i] = v[(i & ~((1 << C) | (1 << T))) | (bc << T) | (bt << C)];
+        }
+    } else {
+        p_copy<A, NR>(v, o);
+    }
+}
+
+
+// out = micro-op u applied to in (every entry of out written)
+template <class R, int NR>
+__device__ __forceinline__ void apply_uop(const typename V2<R>::T (&in)[NR],
+                                          typename V2<R>::T (&out)[NR], const UOp &u,
+                                          const lds<R> *mats, int tid)
+{
+    using A = typename V2<R>::T;
+    const uint32_t code = u.code;
+    if (code < kCodeCX) {
+        R m[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) m[e] = uni(mats[u.mat * 8 + e]);
+#define SVB_P1(J)                                                        \
+    case kCodeMat1 + J: p_mat1<J, A, R, NR>(in, out, m); break;          \
+    case kCodeMat1R + J: p_mat1r<J, A, R, NR>(in, out, m); break;        \
+    case kCodeDiag1 + J: p_diag1<J, A, R, NR>(in, out, m); break;
+        switch (code) { SVB_P1(0) SVB_P1(1) SVB_P1(2) SVB_P1(3) SVB_P1(4) SVB_P1(5) default: p_copy<A, NR>(in, out); }
+#undef SVB_P1
+    } else {
+#define SVB_P2(C, T)                                                     \
+    case kCodeCX + 6 * C + T: p_cx<C, T, A, NR>(in, out); break;         \
+    case kCodeCZ + 6 * C + T: p_cz<C, T, A, NR>(in, out); break;         \
+    case kCodeSwap + 6 * C + T: p_swap<C, T, A, NR>(in, out); break;
+#define SVB_P2ROW(C) SVB_P2(C, 0) SVB_P2(C, 1) SVB_P2(C, 2) SVB_P2(C, 3) SVB_P2(C, 4) SVB_P2(C, 5)
+        switch (code) { SVB_P2ROW(0) SVB_P2ROW(1) SVB_P2ROW(2) SVB_P2ROW(3) SVB_P2ROW(4) SVB_P2ROW(5)
+                        default: p_copy<A, NR>(in, out); }
+#undef SVB_P2ROW
+#undef SVB_P2
+    }
+}
+
+// Register groups whose two register sets fit the budget of two
+// workgroups per compute unit run the alternating form; larger ones
+// (64 complex64 or 32 complex128 amplitudes per thread) update one set
+template <class R, int NR>
+constexpr bool two_sets() { return NR * (int)sizeof(typename V2<R>::T) <= 256; }
+
 // Values the tile loop needs, held in registers: the executor context
 // lives in private memory (cold paths take it by reference), and a private
 // load inside the loop would wait for the tile copies in flight.
@@ -804,7 +976,7 @@ template <class R, int NR> struct Direct;
 // micro-ops in registers, scatter back (to LDS, or with DIRECT to HBM).
 template <class R, int NR, bool DIRECT>
 __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi, int first, int count,
-                                          const Direct<R, NR> &d)
+                                          uint32_t gfl, const Direct<R, NR> &d)
 {
     using A = typename V2<R>::T;
     constexpr int RB = NR == 64 ? 6 : NR == 32 ? 5 : NR == 16 ? 4 : 3;
@@ -842,26 +1014,47 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
     }
     const lds<UOp> *uops = (const lds<UOp> *)(size_t)h.uops;
     const lds<R> *mats = (const lds<R> *)(size_t)h.mats;
-    for (int q = 0; q < count; ++q) {
-        const UOp u = get_uop(uops + first + q);
-        if (u.kind == UK_MAT1 || u.kind == UK_DIAG1 || u.kind == UK_MAT1R) {
-            if constexpr (sizeof(R) == 4) {
-                float a4[4];
-                mfma_rows(mats + u.mat * 8, (uint32_t)h.tid, a4);
-                d_mat1_mfma<NR>(v, u.j0, a4);
-            } else {
-                R m[8];
+    // image of register bit a under the group's closing permutation (the
+    // identity unless the flags carry one)
+    uint32_t img[RB];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) m[e] = uni(mats[u.mat * 8 + e]);
-                d_mat1<A, R, NR>(v, u.j0, m, u.kind);
+    for (int a = 0; a < RB; ++a) img[a] = 1u << a;
+    if constexpr (two_sets<R, NR>()) {
+        A w[NR];
+        for (int q = 0; q < count; q += 2) {  // count is even
+            apply_uop<R, NR>(v, w, get_uop(uops + first + q), mats, h.tid);
+            apply_uop<R, NR>(w, v, get_uop(uops + first + q + 1), mats, h.tid);
+        }
+        if (gfl & kGrpPerm) {
+#pragma unroll
+            for (int a = 0; a < RB; ++a) img[a] = (gfl >> (1 + 5 * a)) & 31u;
+        }
+    } else {
+        for (int q = 0; q < count; ++q) {
+            const UOp u = get_uop(uops + first + q);
+            if (u.code == kCodeCopy) continue;
+            if (u.kind == UK_MAT1 || u.kind == UK_DIAG1 || u.kind == UK_MAT1R) {
+                if constexpr (sizeof(R) == 4) {
+                    float a4[4];
+                    mfma_rows(mats + u.mat * 8, (uint32_t)h.tid, a4);
+                    d_mat1_mfma<NR>(v, u.j0, a4);
+                } else {
+                    R m[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) m[e] = uni(mats[u.mat * 8 + e]);
+                    d_mat1<A, R, NR>(v, u.j0, m, u.kind);
+                }
+            } else {
+                d_two<A, NR>(v, u.kind, u.j0, u.j1);
             }
-        } else {
-            d_two<A, NR>(v, u.kind, u.j0, u.j1);
         }
     }
+    // register i holds group index i; it is stored at the position of the
+    // permuted index: XOR over the set bits a of i of the images img[a]
     if constexpr (DIRECT) {
         // global amplitude offset of tile index x: hi[x >> kCoalesceQ] + (x & kRunMask),
-        // a bit deposit, so the thread part and the register parts add
+        // a bit deposit (register bits and thread bits land on distinct
+        // bits, so parts combine by XOR or addition alike)
         const lds<uint32_t> *hi = (const lds<uint32_t> *)(size_t)h.hi;
         const uint32_t gbase = hi[base >> kCoalesceQ] + (base & kRunMask);
         uint32_t ge[RB];
@@ -870,13 +1063,22 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
             const uint32_t x = 1u << ((gpw[j >> 2] >> (8 * (j & 3))) & 0xffu);
             ge[j] = __builtin_amdgcn_readfirstlane(hi[x >> kCoalesceQ] + (x & kRunMask));
         }
+        uint32_t gi8[RB];
+#pragma unroll
+        for (int a = 0; a < RB; ++a) {
+            uint32_t g = 0;
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                if ((img[a] >> b) & 1u) g ^= ge[b];
+            gi8[a] = g;
+        }
         // uniform part in the scalar base, thread part as the 32-bit vector
         // offset: one address register for all NR stores
         const uint32_t voff = gbase * (uint32_t)sizeof(A);
         uint32_t G[NR];
         G[0] = 0;
 #pragma unroll
-        for (int i = 1; i < NR; ++i) G[i] = G[i & (i - 1)] + ge[__builtin_ctz(i)];
+        for (int i = 1; i < NR; ++i) G[i] = G[i & (i - 1)] ^ gi8[__builtin_ctz(i)];
         gbl<A> *const tile = uni_ptr(d.tile);
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
@@ -884,11 +1086,24 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
             *(gbl<A> *)(sb + voff) = v[i];
         }
     } else {
+        uint32_t pi8[RB];
+#pragma unroll
+        for (int a = 0; a < RB; ++a) {
+            uint32_t p = 0;
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                if ((img[a] >> b) & 1u) p ^= pe8[b];
+            pi8[a] = p;
+        }
+        uint32_t K2[NR];
+        K2[0] = 0;
+#pragma unroll
+        for (int i = 1; i < NR; ++i) K2[i] = K2[i & (i - 1)] ^ pi8[__builtin_ctz(i)];
         // recompute the addresses rather than keep NR of them live
         uint32_t pw = pb8;
         asm volatile("" : "+v"(pw));
 #pragma unroll
-        for (int i = 0; i < NR; ++i) *(lds<A> *)(size_t)(pw ^ K[i]) = v[i];
+        for (int i = 0; i < NR; ++i) *(lds<A> *)(size_t)(pw ^ K2[i]) = v[i];
         lds_sync();
     }
 }
@@ -1025,7 +1240,7 @@ __device__ bool fuse_flush(Ctx<R> &c, int j, uint32_t &pend_set, int &nu, int &n
     u.kind = diag ? UK_DIAG1 : (pm[1] == 0.0 ? UK_MAT1R : UK_MAT1);
     u.j0 = (uint8_t)j;
     u.j1 = 0;
-    u.pad = 0;
+    u.code = 0;
     u.mat = (uint16_t)nm;
     u.pad2 = 0;
     put_uop(c.uops + nu++, u);
@@ -1048,6 +1263,76 @@ __device__ void fuse_factor(Ctx<R> &c, int j, const double *m, double scale, uin
     }
 }
 
+// Thread 0, after a group's micro-ops [first, nu) are built. CX and SWAP
+// micro-ops that commute with every later micro-op of the group (no later
+// micro-op touches their register bits) move to the end, in order, and are
+// taken out: their product P is a permutation of the register index that
+// the group applies by storing register i at the position of P(i). The
+// remaining count is padded to even with a copy. Returns the group flags.
+__device__ __forceinline__ UOp read_uop(const lds<UOp> *p)
+{
+    UOp u;
+    u.kind = p->kind;
+    u.j0 = p->j0;
+    u.j1 = p->j1;
+    u.code = p->code;
+    u.mat = p->mat;
+    u.pad2 = 0;
+    return u;
+}
+
+__device__ uint32_t fold_trailing_perms(lds<UOp> *u, int first, int &nu)
+{
+    const int cnt = nu - first;
+    const int lo = cnt > 64 ? cnt - 64 : 0;
+    uint64_t folded = 0;
+    uint32_t later = 0;  // register bits of the kept micro-ops after position i
+    for (int i = cnt - 1; i >= lo; --i) {
+        const UOp x = read_uop(u + first + i);
+        if (x.code == kCodeCopy) continue;
+        const bool two = x.kind == UK_CX || x.kind == UK_CZ || x.kind == UK_SWAP;
+        const uint32_t bits = (1u << x.j0) | (two ? (1u << x.j1) : 0u);
+        if ((x.kind == UK_CX || x.kind == UK_SWAP) && !(bits & later)) {
+            folded |= 1ull << (i - lo);
+            continue;
+        }
+        later |= bits;
+    }
+    uint32_t img[5] = {1u, 2u, 4u, 8u, 16u};
+    int kept = first;
+    for (int i = 0; i < cnt; ++i) {
+        const UOp x = read_uop(u + first + i);
+        if (i >= lo && ((folded >> (i - lo)) & 1ull)) {
+            for (int a = 0; a < 5; ++a) {
+                const uint32_t bc = (img[a] >> x.j0) & 1u, bt = (img[a] >> x.j1) & 1u;
+                if (x.kind == UK_CX) {
+                    img[a] ^= bc << x.j1;
+                } else {
+                    img[a] = (img[a] & ~((1u << x.j0) | (1u << x.j1))) | (bc << x.j1) | (bt << x.j0);
+                }
+            }
+            continue;
+        }
+        if (x.code == kCodeCopy) continue;
+        put_uop(u + kept++, x);
+    }
+    nu = kept;
+    if ((nu - first) & 1) {
+        UOp cp;
+        cp.kind = 0;
+        cp.j0 = 0;
+        cp.j1 = 0;
+        cp.code = (uint8_t)kCodeCopy;
+        cp.mat = 0;
+        cp.pad2 = 0;
+        put_uop(u + nu++, cp);
+    }
+    if (!folded) return 0u;
+    uint32_t f = kGrpPerm;
+    for (int a = 0; a < 5; ++a) f |= img[a] << (1 + 5 * a);
+    return f;
+}
+
 // Build the register groups and micro-ops of [S.start, S.end) with the
 // pass's decisions; may shorten the pass if LDS capacity runs out.
 template <class R>
@@ -1059,6 +1344,9 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
     uint64_t flops = 0;
     int j = S.start;
     bool cut = false;
+    // groups that run on two register sets (see two_sets): closing
+    // permutations are folded into the stores, counts padded to even
+    const bool pairs = (1u << (P.tile_q - 8)) * sizeof(typename V2<R>::T) <= 256u;
     while (j < S.end && !cut) {
         const uint32_t g = P.ops[j].group;
         const GroupInfo &gi = P.groups[g];
@@ -1068,7 +1356,7 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
             c.ug[ng].gidx = (int)g;
             c.ug[ng].a = a;
             c.ug[ng].b = b;
-            c.ug[ng].fallback = 1;
+            c.ug[ng].flags = kGrpFallback;
             for (int o = a; o < b; ++o) flops += op_flops(P, P.ops[o], c.dec[o - S.start]);
             ++ng;
             j = b;
@@ -1078,9 +1366,10 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
         uint32_t pend_set = 0;
         int o = a;
         for (; o < b; ++o) {
-            // room for this op (<= 3 micro-ops) and the group's final flush (<= 8)
+            // room for this op (<= 3 micro-ops), the group's final flush (<= 8)
+            // and an even-count pad (1)
             constexpr int kMats = kPassMatBytes / (8 * (int)sizeof(R));
-            if (nu + 11 > kMaxPassUops || nm + 11 > kMats) { cut = true; break; }
+            if (nu + 12 > kMaxPassUops || nm + 11 > kMats) { cut = true; break; }
             const DevOp &op = P.ops[o];
             const int d = c.dec[o - S.start];
             const double sc = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
@@ -1118,7 +1407,7 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
                 u.kind = op.kind == DK_CX ? UK_CX : op.kind == DK_CZ ? UK_CZ : UK_SWAP;
                 u.j0 = op.rb[0];
                 u.j1 = op.rb[1];
-                u.pad = 0;
+                u.code = 0;
                 u.mat = 0;
                 u.pad2 = 0;
                 put_uop(c.uops + nu++, u);
@@ -1126,10 +1415,11 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
             }
         }
         for (int jj = 0; jj < 8; ++jj) fuse_flush(c, jj, pend_set, nu, nm, flops);
+        const uint32_t gflags = pairs ? fold_trailing_perms(c.uops, first, nu) : 0u;
         c.ug[ng].gidx = (int)g;
         c.ug[ng].a = first;
         c.ug[ng].b = nu - first;
-        c.ug[ng].fallback = 0;
+        c.ug[ng].flags = gflags;
         ++ng;
         if (cut) {
             S.end = o;
@@ -1970,15 +2260,16 @@ __device__ __forceinline__ bool run_groups(Ctx<R> &c, const Hot &h, const cst<Gr
         const int gidx = (int)uni((uint32_t)gl.gidx);
         const int a = (int)uni((uint32_t)gl.a);
         const int b = (int)uni((uint32_t)gl.b);
-        const int fb = (int)uni((uint32_t)gl.fallback);
+        const uint32_t gfl = uni(gl.flags);
+        const int fb = (int)(gfl & kGrpFallback);
         if (fb) {
             run_fallback<R>(c, a, b);
         } else if constexpr (NR > 0) {
             if (direct && u == h.n_ug - 1) {
-                run_group<R, NR, true>(h, groups[gidx], a, b, d);
+                run_group<R, NR, true>(h, groups[gidx], a, b, gfl, d);
                 stored = true;
             } else {
-                run_group<R, NR, false>(h, groups[gidx], a, b, d);
+                run_group<R, NR, false>(h, groups[gidx], a, b, gfl, d);
             }
         }
     }
