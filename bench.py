@@ -311,10 +311,13 @@ def qft_comparison(n, shots=4000, p=0.01, plain_shots=40):
         print(json.dumps(line), flush=True)
 
 
-def serving_bench(n_requests: int, loads=(0.8,), max_active: int = 4):
+def serving_bench(n_requests: int, loads=(0.8,), max_active: int = 4,
+                  qubits=(8, 24), shots=(100, 100_000)):
     """Serving workload: the seeded Poisson stream of random noisy U3+CX
     circuits (qubits U{8..24}, depth U{10..60}, shots log-uniform in
-    [100, 1e5], depolarizing 1e-3 / 1e-2, complex64), its first n_requests.
+    [100, 1e5], depolarizing 1e-3 / 1e-2, complex64), its first n_requests;
+    `qubits` and `shots` narrow the ranges (a lighter stream of many more
+    requests, for latency percentiles over hundreds of requests).
     First all requests at once (closed loop: capacity), then the same
     requests with Poisson arrivals at each `load` x that capacity (latency).
     `value` is the throughput at the first load."""
@@ -322,7 +325,8 @@ def serving_bench(n_requests: int, loads=(0.8,), max_active: int = 4):
     import paper_2308_03399_amd.serving as SV
 
     def requests(rate):
-        stream = W.serving_stream(n_requests, rate, seed=0)
+        stream = W.serving_stream(n_requests, rate, seed=0, qubit_range=tuple(qubits),
+                                  shots_range=tuple(shots))
         reqs = [SV.Request(circuit=r["circuit"], noise=r["noise"], shots=r["shots"],
                            seed=r["seed"], dtype=r["dtype"], mode="batch", id=r["id"])
                 for r in stream]
@@ -377,8 +381,9 @@ def serving_bench(n_requests: int, loads=(0.8,), max_active: int = 4):
         "data": "synthetic",
         "config": {
             "workload": f"c5_serving: first {n_requests} requests of the seed-0 Poisson "
-                        "stream; qubits U{8..24}, depth U{10..60}, shots log-uniform "
-                        "[100, 1e5]; depolarizing 1e-3 / 1e-2; batch mode",
+                        f"stream; qubits U{{{qubits[0]}..{qubits[1]}}}, depth U{{10..60}}, "
+                        f"shots log-uniform [{shots[0]}, {shots[1]}]; depolarizing "
+                        "1e-3 / 1e-2; batch mode",
             "requests": [{"id": r.id, "qubits": r.n_qubits, "shots": r.shots,
                           "gates": r.gates, "latency_s": round(r.latency, 4),
                           "chunks": len(r.chunks)} for r in first["results"]],
@@ -419,6 +424,10 @@ def main():
                          "requests (closed loop, then Poisson at --serve-loads x its capacity)")
     ap.add_argument("--serve-loads", type=str, default="0.8",
                     help="comma-separated offered loads, as fractions of the closed-loop capacity")
+    ap.add_argument("--serve-qubits", type=str, default="8,24",
+                    help="qubit range of the serving stream (default: the workload's 8,24)")
+    ap.add_argument("--serve-shots", type=str, default="100,100000",
+                    help="shot range of the serving stream (default: the workload's 100,100000)")
     ap.add_argument("--error-sweep", type=str, default="",
                     help="instead of the headline workload: the paper's error-ratio experiment "
                          "(QFT, 4000 shots), comma-separated qubit counts")
@@ -462,7 +471,9 @@ def main():
                           [float(x) for x in args.error_probs.split(",")])
         return
     if args.serve:
-        serving_bench(args.serve, tuple(float(x) for x in args.serve_loads.split(",")))
+        serving_bench(args.serve, tuple(float(x) for x in args.serve_loads.split(",")),
+                      qubits=[int(x) for x in args.serve_qubits.split(",")],
+                      shots=[int(x) for x in args.serve_shots.split(",")])
         return
     if args.qft:
         for n in [int(x) for x in args.qft.split(",")]:

@@ -70,7 +70,7 @@ typedef enum {
     SV_OP_T, SV_OP_TDG,
     SV_OP_U3 = 10,        /* p = {theta, phi, lambda}, OpenQASM 2 U3        */
     SV_OP_CX = 20, SV_OP_CZ, SV_OP_SWAP,
-    SV_OP_UNITARY = 30,   /* 1 or 2 qubits, dense matrix in mat            */
+    SV_OP_UNITARY = 30,   /* 1 to 5 qubits, dense matrix in mat            */
     SV_OP_MEASURE = 40,   /* qubits -> clbits (Sec. IV-A measure)           */
     SV_OP_RESET,          /* measure without record, then back to |0>      */
     SV_OP_MEASURE_RESET,  /* measure -> clbits, then back to |0>           */
@@ -102,7 +102,8 @@ typedef struct {
 /* Pauli channel (Sec. III-B, Table I): n_terms (probability, Pauli string)
  * entries. pauli[j*nq + t] is the code of term j on the gate's qubit t,
  * I=0 X=1 Y=2 Z=3. Probabilities must be >= 0 and sum to 1 within 1e-12;
- * the entry taken is the first whose running sum exceeds the draw. */
+ * the entry taken is the first whose running sum exceeds the draw. nq is
+ * 1 to 5, at most 1024 terms. */
 typedef struct {
     uint32_t nq, n_terms;
     const double *prob;
@@ -111,7 +112,8 @@ typedef struct {
 
 /* Kraus channel (Sec. III-B, Kraus operator): n_mats matrices of
  * (2^nq)^2 complex entries, row-major, interleaved re/im, with
- * sum_j K_j^dagger K_j = I within 1e-10. nq is 1 or 2. */
+ * sum_j K_j^dagger K_j = I within 1e-10. nq is 1 to 5, at most 16
+ * matrices. */
 typedef struct {
     uint32_t nq, n_mats;
     const double *mats;
@@ -181,6 +183,13 @@ sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
  *                  batch mode, where each holds one state, at most as many
  *                  states as fit in 80% of the device memory free at sizing)
  *   "tile_qubits"  qubits per LDS tile, 6..14; 0 = automatic
+ *   "pipeline"     LDS tile buffers of streamed states: -1 automatic (one,
+ *                  with two workgroups per compute unit), 0 one, 1 two (the
+ *                  next tile is fetched while the current one computes)
+ *   "engine"       0 automatic (streamed states: register groups; states
+ *                  resident in LDS: one LDS sweep per op), 1 LDS sweeps
+ *                  everywhere, 2 register groups also for resident states
+ *                  of 10 or more qubits
  *   "program_bytes" device bytes reserved for the op program (default 8 MiB)
  *   "dump_shot"    shot id whose state before the final op is kept for
  *                  sv_get_state; -1 disables (default)
@@ -295,10 +304,18 @@ sv_status sv_get_margins(sv_batch *b, double *margins, size_t n);
  * interleaved re/im doubles, 2^n complex). SV_ESTATE if none was kept. */
 sv_status sv_get_state(sv_batch *b, double *amps, size_t n_amps);
 
+/* Statistics of the last run (sv_stats above): device times, state passes
+ * and the algorithmic bytes they move, reductions, branches and waiting-list
+ * restarts (Sec. IV-B), near-ties. Valid after a successful run, also one of
+ * sv_run_circuit_noalloc. SV_ESTATE before any. */
 sv_status sv_get_stats(sv_batch *b, sv_stats *out);
 
+/* Free the handle (host memory only; the attached arena stays the
+ * caller's). NULL is accepted. */
 sv_status sv_batch_destroy(sv_batch *b);
 
+/* Message of the last failing call on this thread (static storage of the
+ * thread, valid until its next failing call). */
 const char *sv_last_error(void);
 
 #ifdef __cplusplus

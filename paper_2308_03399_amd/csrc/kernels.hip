@@ -979,7 +979,7 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
                                           uint32_t gfl, const Direct<R, NR> &d)
 {
     using A = typename V2<R>::T;
-    constexpr int RB = NR == 64 ? 6 : NR == 32 ? 5 : NR == 16 ? 4 : 3;
+    constexpr int RB = NR >= 64 ? 6 : NR >= 32 ? 5 : NR >= 16 ? 4 : NR >= 8 ? 3 : 2;
     constexpr int SH = sizeof(A) == 8 ? 3 : 4;
     // scalar loads are whole dwords: read the position bytes as words
     const cst<uint32_t> *gw = (const cst<uint32_t> *)&gi;
@@ -2218,7 +2218,7 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
         S.norm_lb = nlb;
         S.n_ug = 0;
         S.pass_flops = 0;
-        if (P.use_groups && !P.resident && j > start) build_uops(c);
+        if (P.use_groups && j > start) build_uops(c);
     }
     __syncthreads();
 }
@@ -2291,7 +2291,29 @@ __device__ void run_sweep(Ctx<R> &c, bool want_reduce)
     const DevOp &rop = P.ops[S.stop_op < P.n_ops ? S.stop_op : 0];
     uint64_t flops = 0;
     if (P.resident) {
-        apply_range(c, flops);
+        bool done = false;
+        if constexpr (NR > 0) {
+            // the whole state sits in LDS (unswizzled): register groups
+            // gather from it and scatter back, with no HBM traffic
+            if (P.use_groups && has_ops) {
+                Hot h;
+                h.ug = (uint32_t)(size_t)c.ug;
+                h.uops = (uint32_t)(size_t)c.uops;
+                h.mats = (uint32_t)(size_t)c.mats;
+                h.lbase = 0;
+                h.hi = (uint32_t)(size_t)c.hi_off;
+                h.swm = 0;
+                h.n_ug = (int)uni((uint32_t)S.n_ug);
+                h.k = k;
+                h.tid = c.tid;
+                TileIO<R, NR> io{};  // no tile copies
+                run_groups<R, NR>(c, h, to_const(P.groups), false,
+                                  Direct<R, NR>{nullptr, nullptr, 0, false, io});
+                flops = S.pass_flops;
+                done = true;
+            }
+        }
+        if (!done) apply_range(c, flops);
         if (want_reduce) reduce_tile(c, rop, acc);
     } else {
         const PassInfo &pi = P.passes[P.ops[S.start].pass];
@@ -2976,11 +2998,15 @@ static hipError_t dispatch(const svb::ExecParams *P, int is_c128, int reg_bits, 
     if (is_c128) {
         if (reg_bits == 5) return launch_one<double, 32>(P, workers, lds, st, occ);
         if (reg_bits == 4) return launch_one<double, 16>(P, workers, lds, st, occ);
+        if (reg_bits == 3) return launch_one<double, 8>(P, workers, lds, st, occ);
+        if (reg_bits == 2) return launch_one<double, 4>(P, workers, lds, st, occ);
         return launch_one<double, 0>(P, workers, lds, st, occ);
     }
     if (reg_bits == 6) return launch_one<float, 64>(P, workers, lds, st, occ);
     if (reg_bits == 5) return launch_one<float, 32>(P, workers, lds, st, occ);
     if (reg_bits == 4) return launch_one<float, 16>(P, workers, lds, st, occ);
+    if (reg_bits == 3) return launch_one<float, 8>(P, workers, lds, st, occ);
+    if (reg_bits == 2) return launch_one<float, 4>(P, workers, lds, st, occ);
     return launch_one<float, 0>(P, workers, lds, st, occ);
 }
 

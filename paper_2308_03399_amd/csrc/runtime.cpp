@@ -169,12 +169,16 @@ static sv_status derive(sv_batch *b)
         b->resident = 0;
         b->tile_q = k;
     }
-    // register groups need 2^k = kWG * 2^r amplitudes per tile
+    // register groups need 2^k = kWG * 2^r amplitudes per tile. A state
+    // resident in LDS can use them from 4 amplitudes per thread (10 qubits)
+    // on when asked for (engine 2); by default its ops run as LDS sweeps,
+    // which measured faster there (the per-op planning dominates)
     const int r = b->tile_q - 8;
-    const bool r_ok = b->dtype == SV_C128 ? (r == 4 || r == 5) : (r >= 4 && r <= 6);
-    b->use_groups = (!b->resident && r_ok && b->opt_engine == 0) ? 1 : 0;
+    const bool r_ok = b->resident ? (r >= 2 && r <= 5 && b->opt_engine == 2)
+                                  : (b->dtype == SV_C128 ? (r == 4 || r == 5) : (r >= 4 && r <= 6));
+    b->use_groups = (r_ok && b->opt_engine != 1) ? 1 : 0;
     b->reg_bits = b->use_groups ? r : 0;
-    b->nbuf = b->use_groups ? nbuf : 1;
+    b->nbuf = (b->use_groups && !b->resident) ? nbuf : 1;
     if (b->mode == SV_MODE_PLAIN) {  // one state, per-op kernels over the whole GPU
         b->use_groups = 0;
         b->reg_bits = 0;
@@ -881,7 +885,8 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
         if (v < -1 || v >= b->shots) return fail(SV_EINVAL, "dump_shot %lld", (long long)v);
         b->dump_shot = v;
     } else if (k == "engine") {
-        if (v < 0 || v > 1) return fail(SV_EINVAL, "engine %lld (0 automatic, 1 LDS sweeps)", (long long)v);
+        if (v < 0 || v > 2)
+            return fail(SV_EINVAL, "engine %lld (0 automatic, 1 LDS sweeps, 2 register groups)", (long long)v);
         b->opt_engine = v;
     } else if (k == "pipeline") {
         if (v < -1 || v > 1) return fail(SV_EINVAL, "pipeline %lld (-1 automatic, 0, 1)", (long long)v);
@@ -1061,8 +1066,9 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
         plan.passes.push_back(pi);
         plan.groups.push_back(gi);
     } else {
-        plan_program(n, b->tile_q, b->reg_bits, b->resident != 0, b->use_groups != 0, swz, xo,
-                     rules, terminal, plan);
+        // a resident state is stored unswizzled
+        plan_program(n, b->tile_q, b->reg_bits, b->resident != 0, b->use_groups != 0,
+                     b->resident ? 0u : swz, xo, rules, terminal, plan);
     }
     const std::vector<PassInfo> &passes = plan.passes;
     std::vector<double> pool;
@@ -1485,8 +1491,8 @@ sv_status svb_debug_plan(int n_qubits, int tile_q, int reg_bits, const sv_op *op
     }
     const bool resident = n_qubits <= tile_q;
     Plan plan;
-    plan_program(n_qubits, resident ? n_qubits : tile_q, reg_bits, resident, reg_bits > 0, 62u, xo,
-                 rules, terminal, plan);
+    plan_program(n_qubits, resident ? n_qubits : tile_q, reg_bits, resident, reg_bits > 0,
+                 resident ? 0u : 62u, xo, rules, terminal, plan);
     *n_out = plan.order.size();
     *n_passes = plan.passes.size();
     *n_groups = plan.groups.size();
