@@ -186,10 +186,11 @@ sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
  *   "pipeline"     LDS tile buffers of streamed states: -1 automatic (one,
  *                  with two workgroups per compute unit), 0 one, 1 two (the
  *                  next tile is fetched while the current one computes)
- *   "engine"       0 automatic (streamed states: register groups; states
- *                  resident in LDS: one LDS sweep per op), 1 LDS sweeps
- *                  everywhere, 2 register groups also for resident states
- *                  of 10 or more qubits
+ *   "engine"       0 automatic (register groups for streamed states and
+ *                  for resident states of 10 or more qubits up to 32 KiB;
+ *                  one LDS sweep per op otherwise), 1 LDS sweeps everywhere,
+ *                  2 register groups for every resident state of 10 or
+ *                  more qubits
  *   "program_bytes" device bytes reserved for the op program (default 8 MiB)
  *   "dump_shot"    shot id whose state before the final op is kept for
  *                  sv_get_state; -1 disables (default)

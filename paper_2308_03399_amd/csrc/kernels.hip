@@ -332,6 +332,19 @@ __device__ __forceinline__ uint32_t svb_side_bytes_dev(int tile_q, int amp_bytes
     return (tile + hi + dec + ua + 15u) / 16u * 16u;
 }
 
+// LDS bytes of the op staging area after the per-workgroup state
+__host__ __device__ __forceinline__ size_t stage_bytes(int stage_cap)
+{
+    if (stage_cap <= 0) return 0;
+    return (size_t)stage_cap * (sizeof(DevOp) + 8 * sizeof(double)) +
+           (kStageRules * sizeof(DevRule) + kStageRules * sizeof(int32_t) + 15) / 16 * 16 +
+           2 * kStageTerms * sizeof(double);
+}
+__host__ __device__ __forceinline__ size_t shared_bytes16()
+{
+    return (sizeof(WgShared) + 15) / 16 * 16;
+}
+
 template <class R>
 struct Ctx {
     using A = typename V2<R>::T;
@@ -348,6 +361,13 @@ struct Ctx {
     lds<UOp> *uops;    // LDS: micro-ops of the pass
     lds<R> *mats;      // LDS: fused matrices of the pass (8 reals each)
     lds<double> *pend; // LDS: pending FP64 2x2 matrices during fusion (8 x 8)
+    const DevOp *sops; // staged op records of the pass (LDS, seen through a generic
+                       // pointer), or null
+    lds<double> *smat; // staged 2x2 matrices (8 doubles) of the staged DK_MAT1 ops
+    int s0, scap;      // first staged op, ops staged
+    const DevRule *srules;  // staged rule records (generic pointer to LDS), or null
+    lds<int32_t> *sroff;    // staged Pauli table offset of each rule
+    lds<double> *sthr;      // staged Pauli thresholds, then the term codes
     uint32_t tsize;    // 2^k
     uint32_t n_tiles;  // 2^(n-k), 1 if resident
     uint32_t swm;      // swizzle mask of the current pass (0: identity)
@@ -359,6 +379,88 @@ struct Ctx {
         return i ^ (((i >> 6) ^ (i >> 12)) & swm);
     }
 };
+
+// Op record j: from the LDS copy of the pass when staged, else from the
+// program in global memory.
+template <class R>
+__device__ __forceinline__ const DevOp &op_at(const Ctx<R> &c, int j)
+{
+    const int i = j - c.s0;
+    return (i >= 0 && i < c.scap) ? c.sops[i] : c.P.ops[j];
+}
+
+// Matrix of one-qubit gate op j (see op_matrix): the staged copy when there is one.
+template <class R>
+__device__ __forceinline__ const double *op_matrix_at(const Ctx<R> &c, int j, const DevOp &op)
+{
+    const int i = j - c.s0;
+    if (i >= 0 && i < c.scap) return (const double *)(c.smat + (size_t)i * 8);
+    return op_matrix(c.P, op, c.S);
+}
+
+// Rule r: the LDS copy when the rules are staged.
+template <class R>
+__device__ __forceinline__ const DevRule &rule_at(const Ctx<R> &c, uint32_t r)
+{
+    return c.srules ? c.srules[r] : c.P.rules[r];
+}
+
+// First Pauli term whose cumulative threshold exceeds u (thresholds from
+// LDS when staged).
+template <class R>
+__device__ __forceinline__ int pauli_pick_c(const Ctx<R> &c, uint32_t r, const DevRule &ru, double u)
+{
+    const int n = (int)ru.n_terms;
+    if (c.srules) {
+        const lds<double> *thr = c.sthr + c.sroff[r];
+        for (int j = 0; j < n; ++j)
+            if (u < thr[j]) return j;
+    } else {
+        const double *thr = c.P.pool + ru.thr;
+        for (int j = 0; j < n; ++j)
+            if (u < thr[j]) return j;
+    }
+    return n - 1;
+}
+
+// Term code of drawn term d (see pauli_code), from LDS when staged.
+template <class R>
+__device__ __forceinline__ uint32_t pauli_code_c(const Ctx<R> &c, uint32_t r, const DevRule &ru, int d)
+{
+    if (c.srules) return (uint32_t)c.sthr[kStageTerms + c.sroff[r] + d];
+    return (uint32_t)c.P.pool[ru.codes + (uint32_t)d];
+}
+
+// All threads, once per workgroup: copy the rule records and the Pauli
+// thresholds and term codes to LDS (the host stages them only when they
+// fit: at most kStageRules rules and kStageTerms Pauli terms).
+template <class R>
+__device__ __noinline__ void stage_rules(Ctx<R> &c)
+{
+    const ExecParams &P = c.P;
+    if (c.tid == 0) {
+        int off = 0;
+        for (int r = 0; r < P.n_rules; ++r) {
+            c.sroff[r] = off;
+            if (!P.rules[r].is_kraus) off += (int)P.rules[r].n_terms;
+        }
+    }
+    constexpr int W = (int)(sizeof(DevRule) / 4);
+    const uint32_t *src = (const uint32_t *)P.rules;
+    lds<uint32_t> *dst = (lds<uint32_t> *)(lds<DevRule> *)c.srules;
+    for (int i = c.tid; i < P.n_rules * W; i += kWG) dst[i] = src[i];
+    __syncthreads();
+    for (int r = 0; r < P.n_rules; ++r) {
+        const DevRule &ru = P.rules[r];
+        if (ru.is_kraus) continue;
+        const int o = c.sroff[r];
+        for (int j = c.tid; j < (int)ru.n_terms; j += kWG) {
+            c.sthr[o + j] = P.pool[ru.thr + j];
+            c.sthr[kStageTerms + o + j] = P.pool[ru.codes + j];
+        }
+    }
+    __syncthreads();
+}
 
 // ----------------------------------------------------------- op sweeps
 template <class R>
@@ -1208,33 +1310,45 @@ struct Direct {
 // matrix collects consecutive one-qubit factors (gate, drawn Pauli, chosen
 // Kraus matrix); two-qubit permutations flush the pending factors of their
 // bits and are emitted as they are.
-__device__ __forceinline__ void m2_mul_left(lds<double> *pm, const double *a)
+// The pending FP64 2x2 matrices live in LDS; each step reads a whole
+// matrix at once into registers (one LDS round trip), works there, and
+// writes it back.
+__device__ __forceinline__ void m2_mul_left(lds<double> *pm, const double (&a)[8])
 {
     // pm <- a * pm (row-major 2x2, interleaved re/im)
-    double o[8];
+    double b[8], o[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b[e] = pm[e];
+#pragma unroll
     for (int r = 0; r < 2; ++r)
+#pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
             double re = 0, im = 0;
+#pragma unroll
             for (int t = 0; t < 2; ++t) {
                 const double ar = a[2 * (2 * r + t)], ai = a[2 * (2 * r + t) + 1];
-                const double br = pm[2 * (2 * t + cc)], bi = pm[2 * (2 * t + cc) + 1];
+                const double br = b[2 * (2 * t + cc)], bi = b[2 * (2 * t + cc) + 1];
                 re += ar * br - ai * bi;
                 im += ar * bi + ai * br;
             }
             o[2 * (2 * r + cc)] = re;
             o[2 * (2 * r + cc) + 1] = im;
         }
+#pragma unroll
     for (int e = 0; e < 8; ++e) pm[e] = o[e];
 }
 
 template <class R>
-__device__ bool fuse_flush(Ctx<R> &c, int j, uint32_t &pend_set, int &nu, int &nm,
-                           uint64_t &flops)
+__device__ __forceinline__ bool fuse_flush(Ctx<R> &c, int j, uint32_t &pend_set, int &nu, int &nm,
+                                           uint64_t &flops)
 {
     if (!((pend_set >> j) & 1u)) return true;
     pend_set &= ~(1u << j);
-    const lds<double> *pm = c.pend + 8 * j;
+    double pm[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) pm[e] = c.pend[8 * j + e];
     const bool diag = pm[2] == 0.0 && pm[3] == 0.0 && pm[4] == 0.0 && pm[5] == 0.0;
+#pragma unroll
     for (int e = 0; e < 8; ++e) c.mats[nm * 8 + e] = (R)pm[e];
     UOp u;
     u.kind = diag ? UK_DIAG1 : (pm[1] == 0.0 ? UK_MAT1R : UK_MAT1);
@@ -1250,14 +1364,17 @@ __device__ bool fuse_flush(Ctx<R> &c, int j, uint32_t &pend_set, int &nu, int &n
 }
 
 template <class R>
-__device__ void fuse_factor(Ctx<R> &c, int j, const double *m, double scale, uint32_t &pend_set)
+__device__ __forceinline__ void fuse_factor(Ctx<R> &c, int j, const double *m, double scale,
+                                            uint32_t &pend_set)
 {
     double a[8];
+#pragma unroll
     for (int e = 0; e < 8; ++e) a[e] = m[e] * scale;
     lds<double> *pm = c.pend + 8 * j;
     if ((pend_set >> j) & 1u) {
         m2_mul_left(pm, a);
     } else {
+#pragma unroll
         for (int e = 0; e < 8; ++e) pm[e] = a[e];
         pend_set |= 1u << j;
     }
@@ -1348,7 +1465,7 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
     // permutations are folded into the stores, counts padded to even
     const bool pairs = (1u << (P.tile_q - 8)) * sizeof(typename V2<R>::T) <= 256u;
     while (j < S.end && !cut) {
-        const uint32_t g = P.ops[j].group;
+        const uint32_t g = op_at(c, j).group;
         const GroupInfo &gi = P.groups[g];
         const int a = j, b = min((int)gi.end_op, S.end);
         if (ng >= kMaxPassGroups) { cut = true; S.end = j; break; }
@@ -1357,7 +1474,7 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
             c.ug[ng].a = a;
             c.ug[ng].b = b;
             c.ug[ng].flags = kGrpFallback;
-            for (int o = a; o < b; ++o) flops += op_flops(P, P.ops[o], c.dec[o - S.start]);
+            for (int o = a; o < b; ++o) flops += op_flops(P, op_at(c, o), c.dec[o - S.start]);
             ++ng;
             j = b;
             continue;
@@ -1370,23 +1487,23 @@ __device__ __noinline__ void build_uops(Ctx<R> &c)
             // and an even-count pad (1)
             constexpr int kMats = kPassMatBytes / (8 * (int)sizeof(R));
             if (nu + 12 > kMaxPassUops || nm + 11 > kMats) { cut = true; break; }
-            const DevOp &op = P.ops[o];
+            const DevOp &op = op_at(c, o);
             const int d = c.dec[o - S.start];
             const double sc = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
             if (op.kind == DK_BFUNC || ((op.flags & DF_COND) && d == kSkip)) continue;
             switch (op.kind) {
             case DK_MAT1:
-                fuse_factor(c, op.rb[0], op_matrix(P, op, S), 1.0, pend_set);
+                fuse_factor(c, op.rb[0], op_matrix_at(c, o, op), 1.0, pend_set);
                 break;
             case DK_KRAUS: {
-                const DevRule &ru = P.rules[op.rule];
+                const DevRule &ru = rule_at(c, op.rule);
                 // c * I: the state is kept unnormalised anyway
                 if (((ru.scalar_mask >> d) & 1u) && sc == 1.0) break;
                 fuse_factor(c, op.rb[0], P.pool + ru.mats + (size_t)d * 8, sc, pend_set);
                 break;
             }
             case DK_PAULI: {
-                const uint32_t code = pauli_code(P, P.rules[op.rule], d);
+                const uint32_t code = pauli_code_c(c, op.rule, rule_at(c, op.rule), d);
                 if (code == 0) break;  // identity
                 for (int t = 0; t < op.nq; ++t) {
                     const uint32_t x = (code >> t) & 1u, z = (code >> (8 + t)) & 1u;
@@ -2093,6 +2210,30 @@ __device__ __noinline__ void split_branch(Ctx<R> &c, const DevOp &op, int j, boo
 }
 
 // Determine the op range of the next sweep (and why it stops).
+// All threads: copy op records [first, first + cnt) of the program, and the
+// matrices of their DK_MAT1 ops, to the LDS staging area, so that the
+// pass's planning and fusion (one thread, op after op) read LDS, not global
+// memory. Ends with a barrier.
+template <class R>
+__device__ __noinline__ void stage_ops(Ctx<R> &c, int first, int cnt)
+{
+    const ExecParams &P = c.P;
+    constexpr int W = (int)(sizeof(DevOp) / 16);
+    const gbl<u32x4> *src = (const gbl<u32x4> *)(P.ops + first);
+    lds<u32x4> *dst = (lds<u32x4> *)(lds<DevOp> *)c.sops;
+    for (int i = c.tid; i < cnt * W; i += kWG) dst[i] = src[i];
+    for (int i = c.tid; i < cnt; i += kWG) {
+        const DevOp &op = P.ops[first + i];
+        if (op.kind != DK_MAT1) continue;
+        const double *m = op_matrix(P, op, c.S);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) c.smat[i * 8 + e] = m[e];
+    }
+    c.s0 = first;
+    c.scap = cnt;
+    __syncthreads();
+}
+
 template <class R>
 __device__ __noinline__ void plan_pass(Ctx<R> &c)
 {
@@ -2109,6 +2250,11 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
     }
     const PassInfo &pi = P.passes[P.ops[start].pass];
     const int end_static = (int)pi.end_op;
+    int lim = kMaxPassOps;  // ops in this pass at most
+    if (P.stage_cap > 0) {
+        lim = min(P.stage_cap, end_static - start);
+        stage_ops(c, start, lim);
+    }
     if (S.pending >= 0) {
         if (tid == 0) c.dec[0] = S.pending;
         ++j;
@@ -2117,15 +2263,16 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
     int stop = STOP_NONE;
     const double lb_floor = sizeof(R) == 4 ? 0x1.0p-30 : 0x1.0p-200;
     for (;;) {
-        while (j < end_static && j - start < kMaxPassOps) {
-            const uint16_t kd = P.ops[j].kind;
+        while (j < end_static && j - start < lim) {
+            const DevOp &oj = op_at(c, j);
+            const uint16_t kd = oj.kind;
             if (kd == DK_PAULI || kd == DK_KRAUS || kd == DK_MEASURE || kd == DK_BFUNC ||
-                (P.ops[j].flags & DF_COND))
+                (oj.flags & DF_COND))
                 break;
             ++j;
         }
-        if (j >= end_static || j - start >= kMaxPassOps) break;
-        const DevOp &op = P.ops[j];
+        if (j >= end_static || j - start >= lim) break;
+        const DevOp &op = op_at(c, j);
         if (op.kind == DK_BFUNC || (op.flags & DF_COND)) {
             const int v = creg_op(c, op);
             if (op.kind == DK_BFUNC || v == 0) {  // done / skipped for every shot
@@ -2148,13 +2295,13 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
             stop = (op.flags & DF_TERMINAL) ? STOP_TERMINAL : STOP_REDUCE;
             break;
         }
-        const DevRule &ru = P.rules[op.rule];
+        const DevRule &ru = rule_at(c, op.rule);
         if (m == 1) {
             // every thread evaluates the single shot's draw (no barrier)
             const uint64_t shot = (uint64_t)P.shot_perm[S.lo];
             const double u = philox_u01(P.seed, P.shot_base + shot, op.r, 0);
             if (op.kind == DK_PAULI) {
-                if (tid == 0) c.dec[j - start] = pauli_pick(P, ru, u);
+                if (tid == 0) c.dec[j - start] = pauli_pick_c(c, op.rule, ru, u);
                 ++j;
                 continue;
             }
@@ -2175,7 +2322,7 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
             const uint64_t shot = (uint64_t)P.shot_perm[i];
             const double u = philox_u01(P.seed, P.shot_base + shot, op.r, 0);
             if (op.kind == DK_PAULI) {
-                const int o = pauli_pick(P, ru, u);
+                const int o = pauli_pick_c(c, op.rule, ru, u);
                 lmin = min(lmin, o);
                 lmax = max(lmax, o);
             } else if (!(u < ru.lam_min0)) {
@@ -2229,7 +2376,7 @@ __device__ void apply_range(Ctx<R> &c, uint64_t &flops)
     const ExecParams &P = c.P;
     lds<WgShared> &S = c.S;
     for (int j = S.start; j < S.end; ++j) {
-        const DevOp &op = P.ops[j];
+        const DevOp &op = op_at(c, j);
         const int d = c.dec[j - S.start];
         const double s = (j == S.start && S.pending >= 0) ? S.first_scale : 1.0;
         apply_op(c, op, d, s);
@@ -2244,7 +2391,7 @@ __device__ __noinline__ void run_fallback(Ctx<R> &c, int a, int b)
     lds<WgShared> &S = c.S;
     for (int o = a; o < b; ++o) {
         const double s = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
-        apply_op(c, c.P.ops[o], c.dec[o - S.start], s);
+        apply_op(c, op_at(c, o), c.dec[o - S.start], s);
     }
 }
 
@@ -2732,6 +2879,20 @@ exec_kernel(ExecParams P)
     c.uops = (lds<UOp> *)(uarea + kMaxPassGroups * sizeof(UGroup));
     c.mats = (lds<R> *)((lds<unsigned char> *)c.uops + kMaxPassUops * sizeof(UOp));
     c.pend = (lds<double> *)((lds<unsigned char> *)c.mats + kPassMatBytes);
+    {
+        // op staging area after the per-workgroup state
+        lds<unsigned char> *st = (lds<unsigned char> *)&S + shared_bytes16();
+        c.sops = P.stage_cap > 0 ? (const DevOp *)(lds<DevOp> *)st : nullptr;
+        c.smat = (lds<double> *)(st + (size_t)P.stage_cap * sizeof(DevOp));
+        c.s0 = 0;
+        c.scap = 0;
+        lds<unsigned char> *sr = (lds<unsigned char> *)(c.smat + (size_t)P.stage_cap * 8);
+        c.srules = P.stage_rules ? (const DevRule *)(lds<DevRule> *)sr : nullptr;
+        c.sroff = (lds<int32_t> *)(sr + kStageRules * sizeof(DevRule));
+        c.sthr = (lds<double> *)(sr + (kStageRules * sizeof(DevRule) + kStageRules * sizeof(int32_t) + 15) /
+                                          16 * 16);
+        if (P.stage_rules) stage_rules(c);
+    }
     if (tid < ST_COUNT) S.st[tid] = 0;
     __syncthreads();
 
@@ -2948,7 +3109,8 @@ static size_t uarea_bytes(int cnt_in_tile)
     return (!cnt_in_tile && cnt > fuse) ? cnt : fuse;
 }
 
-extern "C" size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident, int nbuf)
+extern "C" size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident, int nbuf,
+                                     int stage_cap)
 {
     const size_t tile = ((size_t)1 << tile_q) * amp_bytes;
     const size_t tiles = tile * (resident ? 1 : nbuf);
@@ -2956,7 +3118,7 @@ extern "C" size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident, in
     const size_t dec = svb::kMaxPassOps * 2;
     const int cnt_in_tile = !resident && tile >= 16u * svb::kWG * 4u;
     const size_t side = (tiles + hi + dec + uarea_bytes(cnt_in_tile) + 15) / 16 * 16;
-    return side + sizeof(svb::WgShared);
+    return side + svb::shared_bytes16() + svb::stage_bytes(stage_cap);
 }
 
 extern "C" {
@@ -2992,9 +3154,10 @@ static hipError_t launch_one(const svb::ExecParams *P, int workers, size_t lds, 
 }
 
 static hipError_t dispatch(const svb::ExecParams *P, int is_c128, int reg_bits, int tile_q,
-                           int resident, int nbuf, int workers, hipStream_t st, int *occ)
+                           int resident, int nbuf, int stage_cap, int workers, hipStream_t st,
+                           int *occ)
 {
-    const size_t lds = svb_exec_lds_bytes(tile_q, is_c128 ? 16 : 8, resident, nbuf);
+    const size_t lds = svb_exec_lds_bytes(tile_q, is_c128 ? 16 : 8, resident, nbuf, stage_cap);
     if (is_c128) {
         if (reg_bits == 5) return launch_one<double, 32>(P, workers, lds, st, occ);
         if (reg_bits == 4) return launch_one<double, 16>(P, workers, lds, st, occ);
@@ -3015,13 +3178,15 @@ extern "C" {
 hipError_t svb_launch_exec(const svb::ExecParams *P, int is_c128, int reg_bits, int workers,
                            hipStream_t st)
 {
-    return dispatch(P, is_c128, reg_bits, P->tile_q, P->resident, P->nbuf, workers, st, nullptr);
+    return dispatch(P, is_c128, reg_bits, P->tile_q, P->resident, P->nbuf, P->stage_cap, workers, st,
+                    nullptr);
 }
 
 hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int reg_bits, int nbuf,
-                              int *blocks_per_cu)
+                              int stage_cap, int *blocks_per_cu)
 {
-    return dispatch(nullptr, is_c128, reg_bits, tile_q, resident, nbuf, 0, nullptr, blocks_per_cu);
+    return dispatch(nullptr, is_c128, reg_bits, tile_q, resident, nbuf, stage_cap, 0, nullptr,
+                    blocks_per_cu);
 }
 
 }  // extern "C"

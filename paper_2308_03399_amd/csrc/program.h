@@ -22,6 +22,9 @@ constexpr double kNearTie = 1e-9;    // relative decision margin counted as a ne
 constexpr uint64_t kInfBits = 0x7FF0000000000000ull;  // +inf as double bits
 constexpr uint32_t kRunMask = (1u << kCoalesceQ) - 1;  // contiguous run of a tile in HBM
 constexpr int kMaxTileQ = 14;
+constexpr int kStageOps = 128;       // ops of a pass staged in LDS (resident states)
+constexpr int kStageRules = 16;      // noise rules staged in LDS with them
+constexpr int kStageTerms = 256;     // Pauli terms (thresholds and codes) staged in LDS
 
 // Device op kinds (after noise-site expansion).
 enum DevKind : uint16_t {
@@ -180,6 +183,10 @@ struct ExecParams {
     uint32_t shots_per_set;  // parameter sweep: shots of each set
     int32_t nbuf;            // LDS tile buffers of streamed grouped passes (1, or 2:
                              // the next tile is fetched while this one computes)
+    int32_t stage_cap;       // > 0: a pass's op records (at most this many) and their
+                             // one-qubit matrices are copied to LDS before it is planned
+    int32_t n_rules;         // noise rules of the program
+    int32_t stage_rules;     // 1: the rules and their Pauli tables are copied to LDS once
 };
 
 }  // namespace svb

@@ -30,8 +30,8 @@ hipError_t svb_launch_restart(const ExecParams *P, int n_wait, hipStream_t st);
 hipError_t svb_launch_exec(const ExecParams *P, int is_c128, int reg_bits, int workers,
                            hipStream_t st);
 hipError_t svb_exec_occupancy(int is_c128, int tile_q, int resident, int reg_bits, int nbuf,
-                              int *blocks_per_cu);
-size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident, int nbuf);
+                              int stage_cap, int *blocks_per_cu);
+size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int resident, int nbuf, int stage_cap);
 hipError_t svb_counts(const uint64_t *memory, int64_t n, void *temp, size_t temp_bytes,
                       uint64_t *keys_sorted, uint64_t *uniq, uint32_t *cnt, uint32_t *n_uniq,
                       hipStream_t st);
@@ -101,6 +101,7 @@ struct sv_batch {
     int64_t opt_engine = 0;            // 0 automatic, 1 LDS sweeps only
     int64_t opt_pipeline = -1;         // -1 automatic, 0 one tile buffer, 1 two
     int nbuf = 1;                      // LDS tile buffers of grouped streamed passes
+    int stage_cap = 0;                 // ops of a pass staged in LDS (resident register groups)
     int cus = 0;
     int64_t wallclock_khz = 100000;
     int64_t auto_slots = 0;            // branch mode's automatic slot count, fixed at first sizing
@@ -150,7 +151,7 @@ static sv_status derive(sv_batch *b)
     // tile; one buffer: two workgroups per compute unit overlap instead
     int nbuf = b->opt_pipeline == 0 ? 1 : (b->opt_pipeline == 1 ? 2 : kAutoTileBuffers);
     auto fits = [&](int kk, int nb, int per_cu) {
-        return (size_t)per_cu * (svb_exec_lds_bytes(kk, amp_bytes(b), 0, nb) + static_lds) <= lds_cap;
+        return (size_t)per_cu * (svb_exec_lds_bytes(kk, amp_bytes(b), 0, nb, 0) + static_lds) <= lds_cap;
     };
     int kmax = b->dtype == SV_C128 ? 13 : kMaxTileQ;
     while (kmax > 6 && !fits(kmax, nbuf, 1)) --kmax;
@@ -170,15 +171,20 @@ static sv_status derive(sv_batch *b)
         b->tile_q = k;
     }
     // register groups need 2^k = kWG * 2^r amplitudes per tile. A state
-    // resident in LDS can use them from 4 amplitudes per thread (10 qubits)
-    // on when asked for (engine 2); by default its ops run as LDS sweeps,
-    // which measured faster there (the per-op planning dominates)
+    // resident in LDS uses them from 4 amplitudes per thread (10 qubits) on
+    // when its passes can be staged in LDS (states of at most 32 KiB) or
+    // when asked for (engine 2); larger resident states run their ops as
+    // LDS sweeps by default, which measured faster without staging
     const int r = b->tile_q - 8;
-    const bool r_ok = b->resident ? (r >= 2 && r <= 5 && b->opt_engine == 2)
+    const bool small = state_bytes(b) <= (32u << 10);
+    const bool r_ok = b->resident ? (r >= 2 && r <= 5 && (b->opt_engine == 2 || small))
                                   : (b->dtype == SV_C128 ? (r == 4 || r == 5) : (r >= 4 && r <= 6));
     b->use_groups = (r_ok && b->opt_engine != 1) ? 1 : 0;
     b->reg_bits = b->use_groups ? r : 0;
     b->nbuf = (b->use_groups && !b->resident) ? nbuf : 1;
+    // a resident state planned into register groups copies each pass's op
+    // records to LDS first, when the state is small enough to leave room
+    b->stage_cap = (b->use_groups && b->resident && state_bytes(b) <= (32u << 10)) ? kStageOps : 0;
     if (b->mode == SV_MODE_PLAIN) {  // one state, per-op kernels over the whole GPU
         b->use_groups = 0;
         b->reg_bits = 0;
@@ -188,6 +194,7 @@ static sv_status derive(sv_batch *b)
     }
     int per_cu = 0;
     HIPCHK(svb_exec_occupancy(b->dtype == SV_C128, b->tile_q, b->resident, b->reg_bits, b->nbuf,
+                              b->stage_cap,
                               &per_cu));
     if (per_cu < 1) return fail(SV_EDEVICE, "executor does not fit on a compute unit");
     int64_t w = b->opt_workers > 0 ? b->opt_workers : (int64_t)per_cu * b->cus;
@@ -1215,6 +1222,15 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     P.use_groups = b->use_groups;
     P.swz = swz;
     P.nbuf = b->nbuf;
+    P.stage_cap = b->stage_cap;
+    P.n_rules = (int32_t)drules.size();
+    {
+        int terms = 0;
+        for (const DevRule &r : drules)
+            if (!r.is_kraus) terms += (int)r.n_terms;
+        P.stage_rules = (b->stage_cap > 0 && drules.size() <= (size_t)kStageRules &&
+                         terms <= kStageTerms) ? 1 : 0;
+    }
     P.set_stride = set_stride;
     P.shots_per_set = sweep ? (uint32_t)((uint64_t)b->shots / n_sets) : 1u;
 

@@ -11,8 +11,8 @@ extern "C" {
 hipError_t svb_launch_init(const void *, int, int, int, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t svb_launch_restart(const void *, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t svb_launch_exec(const void *, int, int, int, hipStream_t) { return hipErrorNoDevice; }
-hipError_t svb_exec_occupancy(int, int, int, int, int, int *blocks) { *blocks = 0; return hipErrorNoDevice; }
-size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int, int nbuf)
+hipError_t svb_exec_occupancy(int, int, int, int, int, int, int *blocks) { *blocks = 0; return hipErrorNoDevice; }
+size_t svb_exec_lds_bytes(int tile_q, int amp_bytes, int, int nbuf, int)
 {
     return ((size_t)amp_bytes << tile_q) * (size_t)nbuf;
 }
