@@ -436,6 +436,8 @@ def main():
                     help="for profilers: one sv_run_circuit of this many shots of --workload, "
                          "its stats as one JSON line")
     ap.add_argument("--tile-qubits", type=int, default=0)
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each step's launches from the handle's HIP graph")
     ap.add_argument("--copy-calibrate", type=int, default=0,
                     help="for counter calibration: a device copy of this many MiB, 3 times")
     args = ap.parse_args()
@@ -484,7 +486,8 @@ def main():
     circ, noise, seed = w["circuit"], w["noise"], w["seed"]
     gates = W.count_gates(circ)
     B = args.shots_per_step
-    sim = Simulator(circ["n_qubits"], B, dtype=args.dtype, mode=args.mode)
+    sim = Simulator(circ["n_qubits"], B, dtype=args.dtype, mode=args.mode,
+                    **({"graph": 1} if args.graph else {}))
     stream = sim.stream
 
     def step(idx):
@@ -562,6 +565,8 @@ def main():
             "tile_qubits": stats[0]["tile_qubits"],
             "workers": stats[0]["workers"],
             "passes_per_shot": round(sum(s["passes"] for s in stats) / total_shots, 2),
+            "graph_replays": sum(s["graph_replays"] for s in stats),
+            "program_uploads": sum(s["program_uploads"] for s in stats),
         },
         "roofline": roof,
     }

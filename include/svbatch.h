@@ -161,6 +161,11 @@ typedef struct {
     uint64_t near_ties;        /* state-dependent decisions (Kraus, measure, final
                                   sample) whose relative margin is below 1e-9:
                                   see sv_get_margins                               */
+    uint32_t graph_replays;    /* 1 if the run's initialisation and executor
+                                  launches were replayed from the handle's HIP
+                                  graph (option "graph"), else 0                   */
+    uint32_t program_uploads;  /* 1 if the op program was copied to the device
+                                  (0: unchanged since the last graph run)          */
 } sv_stats;
 
 /* Create a handle for n_qubits (1..30) and n_shots (>= 1) in the given
@@ -203,6 +208,12 @@ sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
  *   "spin_elapsed" 1: the bound above counts from the start of each wait,
  *                  whatever the other workgroups do (forces the failure
  *                  path from the host in tests); 0 (default): watchdog
+ *   "graph"        1: a run's two launches (initialisation, then the
+ *                  persistent executor) are kept as a HIP graph on the handle;
+ *                  later runs update the launch arguments (seed, shot offset,
+ *                  program) and replay it, and skip the program upload when
+ *                  the program is unchanged. Waiting-list relaunches (branch
+ *                  mode) run outside the graph. 0 (default): direct launches
  *   "shot_offset"  global id of shot 0 (default 0): shot i of the handle draws
  *                  the randoms of global shot shot_offset + i, so a large job
  *                  can run as consecutive waves, or be split across devices,

@@ -3131,6 +3131,40 @@ hipError_t svb_launch_init(const svb::ExecParams *P, int restart, int n_root, in
     return hipGetLastError();
 }
 
+// Kernel nodes of a graph-replayed run: function, grid, block and dynamic
+// LDS of the initialisation kernel and of the executor instantiation that
+// svb_launch_exec would launch (the executor's LDS attribute is set here).
+hipError_t svb_graph_nodes(const svb::ExecParams *P, int is_c128, int reg_bits, int workers,
+                           void **init_fn, unsigned *init_grid, void **exec_fn,
+                           unsigned *exec_grid, unsigned *block, size_t *exec_lds)
+{
+    *init_fn = (void *)svb::init_kernel;
+    *init_grid = 1024;
+    *block = svb::kWG;
+    *exec_grid = (unsigned)workers;
+    *exec_lds = svb_exec_lds_bytes(P->tile_q, is_c128 ? 16 : 8, P->resident, P->nbuf, P->stage_cap);
+    void *fn = nullptr;
+#define SVB_FN(RT, N) fn = (void *)svb::exec_kernel<RT, N>
+    if (is_c128) {
+        if (reg_bits == 5) SVB_FN(double, 32);
+        else if (reg_bits == 4) SVB_FN(double, 16);
+        else if (reg_bits == 3) SVB_FN(double, 8);
+        else if (reg_bits == 2) SVB_FN(double, 4);
+        else SVB_FN(double, 0);
+    } else {
+        if (reg_bits == 6) SVB_FN(float, 64);
+        else if (reg_bits == 5) SVB_FN(float, 32);
+        else if (reg_bits == 4) SVB_FN(float, 16);
+        else if (reg_bits == 3) SVB_FN(float, 8);
+        else if (reg_bits == 2) SVB_FN(float, 4);
+        else SVB_FN(float, 0);
+    }
+#undef SVB_FN
+    *exec_fn = fn;
+    return hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)*exec_lds);
+}
+
 hipError_t svb_launch_restart(const svb::ExecParams *P, int n_wait, hipStream_t st)
 {
     hipLaunchKernelGGL(svb::restart_kernel, dim3(256), dim3(256), 0, st, *P, n_wait);

@@ -37,6 +37,9 @@ hipError_t svb_counts(const uint64_t *memory, int64_t n, void *temp, size_t temp
                       hipStream_t st);
 size_t svb_counts_temp_bytes(int64_t n);
 hipError_t svb_noalloc_scratch(void **ptr, uint64_t *bytes);
+hipError_t svb_graph_nodes(const ExecParams *P, int is_c128, int reg_bits, int workers,
+                           void **init_fn, unsigned *init_grid, void **exec_fn,
+                           unsigned *exec_grid, unsigned *block, size_t *exec_lds);
 hipError_t svb_plain_run(int is_c128, const DevOp *ops, const DevOp *hops, int n_ops,
                          const DevRule *rules, const DevRule *hrules, const double *pool, int n,
                          uint64_t n_shots, uint64_t shot_base, uint64_t seed, void *state,
@@ -107,6 +110,16 @@ struct sv_batch {
     int64_t auto_slots = 0;            // branch mode's automatic slot count, fixed at first sizing
     int64_t auto_workers = 0;          // batch mode's memory-bounded worker count, same
     bool no_counts = false;            // no room reserved for the counts histogram
+    int64_t opt_graph = 0;             // 1: launches replayed from a HIP graph
+    bool noalloc_run = false;          // inside sv_run_circuit_noalloc
+    hipGraph_t graph = nullptr;        // [init kernel] -> [executor]
+    hipGraphExec_t gexec = nullptr;
+    hipGraphNode_t n_init = nullptr, n_exec = nullptr;
+    const void *graph_fn = nullptr;    // executor instantiation, grid and LDS the graph holds
+    unsigned graph_grid = 0;
+    size_t graph_lds = 0;
+    uint64_t prog_hash = 0;            // program last uploaded by a graph run (0: none)
+    char *prog_arena = nullptr;        // arena it was uploaded to
     // arena
     bool attached = false;
     char *arena = nullptr;
@@ -898,6 +911,9 @@ sv_status sv_batch_set_option(sv_batch *b, const char *key, int64_t v)
     } else if (k == "pipeline") {
         if (v < -1 || v > 1) return fail(SV_EINVAL, "pipeline %lld (-1 automatic, 0, 1)", (long long)v);
         b->opt_pipeline = v;
+    } else if (k == "graph") {
+        if (v < 0 || v > 1) return fail(SV_EINVAL, "graph %lld (0 or 1)", (long long)v);
+        b->opt_graph = v;
     } else if (k == "shot_offset") {
         if (v < 0) return fail(SV_EINVAL, "shot_offset %lld", (long long)v);
         b->shot_offset = v;
@@ -988,6 +1004,71 @@ static sv_status run_empty(sv_batch *b)
     b->have_results = true;
     b->have_stats = true;
     b->have_dump = b->dump_shot >= 0;
+    return SV_OK;
+}
+
+// FNV-1a hash of the op program (graph runs skip an unchanged upload)
+static uint64_t blob_hash(const std::vector<char> &v)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (char ch : v) h = (h ^ (uint8_t)ch) * 1099511628211ull;
+    return h ? h : 1;
+}
+
+static void graph_drop(sv_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->n_init = b->n_exec = nullptr;
+    b->graph_fn = nullptr;
+}
+
+// The run's initialisation and first executor launch as the handle's HIP
+// graph: built once per executor instantiation, grid and LDS size; later
+// runs only update the two kernel nodes' arguments, then replay it.
+static sv_status graph_run(sv_batch *b, const ExecParams &P, int root_slot, int n_free)
+{
+    void *init_fn = nullptr, *exec_fn = nullptr;
+    unsigned ig = 0, eg = 0, blk = 0;
+    size_t lds = 0;
+    HIPCHK(svb_graph_nodes(&P, b->dtype == SV_C128, b->reg_bits, b->workers, &init_fn, &ig, &exec_fn,
+                           &eg, &blk, &lds));
+    ExecParams Pc = P;
+    int restart = 0, n_root = (int)b->shots, rs = root_slot, nf = n_free;
+    void *iargs[] = {&Pc, &restart, &n_root, &rs, &nf};
+    void *eargs[] = {&Pc};
+    hipKernelNodeParams ip;
+    std::memset(&ip, 0, sizeof ip);
+    ip.func = init_fn;
+    ip.gridDim = dim3(ig);
+    ip.blockDim = dim3(blk);
+    ip.sharedMemBytes = 0;
+    ip.kernelParams = iargs;
+    ip.extra = nullptr;
+    hipKernelNodeParams ep;
+    std::memset(&ep, 0, sizeof ep);
+    ep.func = exec_fn;
+    ep.gridDim = dim3(eg);
+    ep.blockDim = dim3(blk);
+    ep.sharedMemBytes = (unsigned)lds;
+    ep.kernelParams = eargs;
+    ep.extra = nullptr;
+    if (b->gexec && b->graph_fn == exec_fn && b->graph_grid == eg && b->graph_lds == lds) {
+        HIPCHK(hipGraphExecKernelNodeSetParams(b->gexec, b->n_init, &ip));
+        HIPCHK(hipGraphExecKernelNodeSetParams(b->gexec, b->n_exec, &ep));
+    } else {
+        graph_drop(b);
+        HIPCHK(hipGraphCreate(&b->graph, 0));
+        HIPCHK(hipGraphAddKernelNode(&b->n_init, b->graph, nullptr, 0, &ip));
+        HIPCHK(hipGraphAddKernelNode(&b->n_exec, b->graph, &b->n_init, 1, &ep));
+        HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+        b->graph_fn = exec_fn;
+        b->graph_grid = eg;
+        b->graph_lds = lds;
+    }
+    HIPCHK(hipGraphLaunch(b->gexec, b->stream));
     return SV_OK;
 }
 
@@ -1181,7 +1262,18 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
                 plan.groups.size() * sizeof(GroupInfo));
     char *A = b->arena;
     const auto &L = b->lay;
-    HIPCHK(hipMemcpyAsync(A + L.prog, blob.data(), blob.size(), hipMemcpyHostToDevice, b->stream));
+    const bool use_graph = b->opt_graph != 0 && !b->noalloc_run && b->mode != SV_MODE_PLAIN;
+    bool uploaded = true;
+    if (use_graph) {
+        const uint64_t h = blob_hash(blob);
+        uploaded = !(h == b->prog_hash && b->prog_arena == A);
+        b->prog_hash = h;
+        b->prog_arena = A;
+    } else {
+        b->prog_hash = 0;  // the next graph run uploads again
+    }
+    if (uploaded)
+        HIPCHK(hipMemcpyAsync(A + L.prog, blob.data(), blob.size(), hipMemcpyHostToDevice, b->stream));
 
     ExecParams P;
     std::memset(&P, 0, sizeof P);
@@ -1286,12 +1378,19 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     uint64_t acc[ST_COUNT] = {0};
     uint64_t restarts = 0;
     HIPCHK(ev_record(b->ev0, b->stream));
-    HIPCHK(svb_launch_init(&P, 0, (int)b->shots, root_slot, n_free, b->stream));
+    if (!use_graph) HIPCHK(svb_launch_init(&P, 0, (int)b->shots, root_slot, n_free, b->stream));
     double exec_ms = 0;
     uint32_t exec_launches = 0;
     for (;;) {
         HIPCHK(ev_record(b->ev2, b->stream));
-        HIPCHK(svb_launch_exec(&P, b->dtype == SV_C128, b->reg_bits, b->workers, b->stream));
+        if (use_graph && exec_launches == 0) {
+            // initialisation + executor from the graph (exec_ms then includes
+            // the initialisation kernel, a few microseconds)
+            s = graph_run(b, P, root_slot, n_free);
+            if (s != SV_OK) return s;
+        } else {
+            HIPCHK(svb_launch_exec(&P, b->dtype == SV_C128, b->reg_bits, b->workers, b->stream));
+        }
         HIPCHK(ev_record(b->ev3, b->stream));
         Control ctl;
         HIPCHK(hipMemcpyAsync(&ctl, P.ctl, sizeof ctl, hipMemcpyDeviceToHost, b->stream));
@@ -1334,6 +1433,8 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     st.uops = acc[ST_UOPS];
     st.near_ties = acc[ST_NEARTIES];
     st.exec_launches = exec_launches;
+    st.graph_replays = use_graph ? 1u : 0u;
+    st.program_uploads = uploaded ? 1u : 0u;
     b->have_results = true;
     b->have_stats = true;
     b->have_dump = b->dump_shot >= 0;
@@ -1392,7 +1493,9 @@ sv_status sv_run_circuit_noalloc(sv_batch *b, const sv_op *ops, size_t n_ops,
         b->arena_bytes = cap;
         b->stream = (hipStream_t)hip_stream;
         b->attached = true;
+        b->noalloc_run = true;
         s = run_impl(b, ops, n_ops, nm, seed, nullptr, 1);
+        b->noalloc_run = false;
         if (s == SV_OK) {
             const hipError_t e1 = hipMemcpyAsync(memory_out, b->arena + b->lay.memory, n_memory * 8,
                                                  hipMemcpyDeviceToHost, b->stream);
@@ -1540,6 +1643,7 @@ sv_status sv_batch_destroy(sv_batch *b)
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->ev2) (void)hipEventDestroy(b->ev2);
     if (b->ev3) (void)hipEventDestroy(b->ev3);
+    graph_drop(b);
     delete b;
     return SV_OK;
 }

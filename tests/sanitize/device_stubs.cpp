@@ -23,6 +23,11 @@ hipError_t svb_counts(const uint64_t *, int64_t, void *, size_t, uint64_t *, uin
 }
 size_t svb_counts_temp_bytes(int64_t n) { return (size_t)n * 8; }
 hipError_t svb_noalloc_scratch(void **, uint64_t *) { return hipErrorNoDevice; }
+hipError_t svb_graph_nodes(const void *, int, int, int, void **, unsigned *, void **, unsigned *,
+                           unsigned *, size_t *)
+{
+    return hipErrorNoDevice;
+}
 hipError_t svb_plain_run(int, const void *, const void *, int, const void *, const void *, const double *,
                          int, uint64_t, uint64_t, uint64_t, void *, uint64_t *, uint64_t *, double *, int,
                          double *, void *, double, double, hipStream_t)
