@@ -1076,9 +1076,9 @@ template <class R, int NR> struct Direct;
 
 // Gather the thread's NR amplitudes of group gi from LDS, run the group's
 // micro-ops in registers, scatter back (to LDS, or with DIRECT to HBM).
-template <class R, int NR, bool DIRECT>
+template <class R, int NR>
 __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi, int first, int count,
-                                          uint32_t gfl, const Direct<R, NR> &d)
+                                          uint32_t gfl, bool direct, const Direct<R, NR> &d)
 {
     using A = typename V2<R>::T;
     constexpr int RB = NR >= 64 ? 6 : NR >= 32 ? 5 : NR >= 16 ? 4 : NR >= 8 ? 3 : 2;
@@ -1110,7 +1110,7 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
     A v[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) v[i] = *(const lds<A> *)(size_t)(pb8 ^ K[i]);
-    if constexpr (DIRECT) {
+    if (direct) {
         lds_sync();  // every thread has its amplitudes: the buffer is free
         if (d.issue_next) d.io.issue(d.state, d.next_base, 0);
     }
@@ -1152,8 +1152,9 @@ __device__ __forceinline__ void run_group(const Hot &h, const cst<GroupInfo> &gi
         }
     }
     // register i holds group index i; it is stored at the position of the
-    // permuted index: XOR over the set bits a of i of the images img[a]
-    if constexpr (DIRECT) {
+    // permuted index: XOR over the set bits a of i of the images img[a].
+    // One copy of the group body serves both stores (a smaller hot loop)
+    if (direct) {
         // global amplitude offset of tile index x: hi[x >> kCoalesceQ] + (x & kRunMask),
         // a bit deposit (register bits and thread bits land on distinct
         // bits, so parts combine by XOR or addition alike)
@@ -2412,12 +2413,9 @@ __device__ __forceinline__ bool run_groups(Ctx<R> &c, const Hot &h, const cst<Gr
         if (fb) {
             run_fallback<R>(c, a, b);
         } else if constexpr (NR > 0) {
-            if (direct && u == h.n_ug - 1) {
-                run_group<R, NR, true>(h, groups[gidx], a, b, gfl, d);
-                stored = true;
-            } else {
-                run_group<R, NR, false>(h, groups[gidx], a, b, gfl, d);
-            }
+            const bool last_direct = direct && u == h.n_ug - 1;
+            run_group<R, NR>(h, groups[gidx], a, b, gfl, last_direct, d);
+            stored = stored || last_direct;
         }
     }
     return stored;
