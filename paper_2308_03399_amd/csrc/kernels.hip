@@ -325,7 +325,7 @@ __device__ __forceinline__ uint32_t svb_side_bytes_dev(int tile_q, int amp_bytes
     const uint32_t hi = resident ? 16u : (1u << (tile_q - kCoalesceQ)) * 4u;
     const uint32_t dec = kMaxPassOps * 2;
     const uint32_t fuse = kMaxPassGroups * (uint32_t)sizeof(UGroup) + kMaxPassUops * (uint32_t)sizeof(UOp) +
-                          kPassMatBytes + 8 * 8 * 8;
+                          kPassMatBytes;
     const uint32_t cnt = 16u * kWG * 4u;
     const bool cnt_in_tile = !resident && (1u << tile_q) * amp_bytes >= cnt;
     const uint32_t ua = (!cnt_in_tile && cnt > fuse) ? cnt : fuse;
@@ -360,7 +360,6 @@ struct Ctx {
     lds<UGroup> *ug;   // LDS: register groups of the pass
     lds<UOp> *uops;    // LDS: micro-ops of the pass
     lds<R> *mats;      // LDS: fused matrices of the pass (8 reals each)
-    lds<double> *pend; // LDS: pending FP64 2x2 matrices during fusion (8 x 8)
     const DevOp *sops; // staged op records of the pass (LDS, seen through a generic
                        // pointer), or null
     lds<double> *smat; // staged 2x2 matrices (8 doubles) of the staged DK_MAT1 ops
@@ -1307,19 +1306,23 @@ struct Direct {
     TileIO<R, NR> io;
 };
 
-// ---- plan-time fusion (thread 0): per register bit a pending FP64 2x2
-// matrix collects consecutive one-qubit factors (gate, drawn Pauli, chosen
-// Kraus matrix); two-qubit permutations flush the pending factors of their
-// bits and are emitted as they are.
-// The pending FP64 2x2 matrices live in LDS; each step reads a whole
-// matrix at once into registers (one LDS round trip), works there, and
-// writes it back.
-__device__ __forceinline__ void m2_mul_left(lds<double> *pm, const double (&a)[8])
+// ---- plan-time fusion: per register bit a pending FP64 2x2 matrix
+// collects consecutive one-qubit factors (gate, drawn Pauli, chosen Kraus
+// matrix); two-qubit permutations flush the pending factors of their bits
+// and are emitted as they are. Register groups are independent, so each
+// group is fused by its own lane of the first wave, with its pending
+// matrices in that lane's registers.
+constexpr int kMaxRegBits = 6;  // register bits of a group (64 amplitudes per thread)
+
+struct PendRegs {
+    double m[kMaxRegBits][8];  // row-major 2x2, interleaved re/im
+    uint32_t set;              // bit j: m[j] holds a pending product
+};
+
+__device__ __forceinline__ void m2_mul_left(double (&pm)[8], const double (&a)[8])
 {
-    // pm <- a * pm (row-major 2x2, interleaved re/im)
-    double b[8], o[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) b[e] = pm[e];
+    // pm <- a * pm
+    double o[8];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -1328,7 +1331,7 @@ __device__ __forceinline__ void m2_mul_left(lds<double> *pm, const double (&a)[8
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 const double ar = a[2 * (2 * r + t)], ai = a[2 * (2 * r + t) + 1];
-                const double br = b[2 * (2 * t + cc)], bi = b[2 * (2 * t + cc) + 1];
+                const double br = pm[2 * (2 * t + cc)], bi = pm[2 * (2 * t + cc) + 1];
                 re += ar * br - ai * bi;
                 im += ar * bi + ai * br;
             }
@@ -1339,18 +1342,38 @@ __device__ __forceinline__ void m2_mul_left(lds<double> *pm, const double (&a)[8
     for (int e = 0; e < 8; ++e) pm[e] = o[e];
 }
 
-template <class R>
-__device__ __forceinline__ bool fuse_flush(Ctx<R> &c, int j, uint32_t &pend_set, int &nu, int &nm,
-                                           uint64_t &flops)
+// Multiply factor m * scale into the pending matrix of register bit j.
+__device__ __forceinline__ void fuse_factor(PendRegs &p, int j, const double *m, double scale)
 {
-    if (!((pend_set >> j) & 1u)) return true;
-    pend_set &= ~(1u << j);
+    double a[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a[e] = m[e] * scale;
+    if ((p.set >> j) & 1u) {
+        m2_mul_left(p.m[j], a);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) p.m[j][e] = a[e];
+    }
+    p.set |= 1u << j;
+}
+
+// Emit the pending matrix of bit j (if any) as a one-qubit micro-op. Writes
+// stay below the group's micro-op and matrix limits ul, ml; the counts nu,
+// nm advance regardless, so an overrun shows in them.
+template <class R>
+__device__ __forceinline__ void fuse_flush(Ctx<R> &c, PendRegs &p, int j, int &nu, int &nm, int ul,
+                                           int ml, uint64_t &flops)
+{
+    if (!((p.set >> j) & 1u)) return;
+    p.set &= ~(1u << j);
     double pm[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) pm[e] = c.pend[8 * j + e];
+    for (int e = 0; e < 8; ++e) pm[e] = p.m[j][e];
     const bool diag = pm[2] == 0.0 && pm[3] == 0.0 && pm[4] == 0.0 && pm[5] == 0.0;
+    if (nm < ml) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) c.mats[nm * 8 + e] = (R)pm[e];
+        for (int e = 0; e < 8; ++e) c.mats[nm * 8 + e] = (R)pm[e];
+    }
     UOp u;
     u.kind = diag ? UK_DIAG1 : (pm[1] == 0.0 ? UK_MAT1R : UK_MAT1);
     u.j0 = (uint8_t)j;
@@ -1358,30 +1381,13 @@ __device__ __forceinline__ bool fuse_flush(Ctx<R> &c, int j, uint32_t &pend_set,
     u.code = 0;
     u.mat = (uint16_t)nm;
     u.pad2 = 0;
-    put_uop(c.uops + nu++, u);
+    if (nu < ul) put_uop(c.uops + nu, u);
+    ++nu;
     ++nm;
     flops += diag ? 6 : (pm[1] == 0.0 ? 12 : 14);
-    return true;
 }
 
-template <class R>
-__device__ __forceinline__ void fuse_factor(Ctx<R> &c, int j, const double *m, double scale,
-                                            uint32_t &pend_set)
-{
-    double a[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) a[e] = m[e] * scale;
-    lds<double> *pm = c.pend + 8 * j;
-    if ((pend_set >> j) & 1u) {
-        m2_mul_left(pm, a);
-    } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) pm[e] = a[e];
-        pend_set |= 1u << j;
-    }
-}
-
-// Thread 0, after a group's micro-ops [first, nu) are built. CX and SWAP
+// The lane that built a group, after its micro-ops [first, nu) are built. CX and SWAP
 // micro-ops that commute with every later micro-op of the group (no later
 // micro-op touches their register bits) move to the end, in order, and are
 // taken out: their product P is a permutation of the register index that
@@ -1451,105 +1457,244 @@ __device__ uint32_t fold_trailing_perms(lds<UOp> *u, int first, int &nu)
     return f;
 }
 
+// Micro-ops and matrices that ops [a, b) of a register group produce
+// before trailing permutations are folded: they follow from the op kinds,
+// register bits and decisions alone. Stops before the first op o at which
+// fewer than 12 micro-op slots (the op's three, a final flush of eight and
+// an even-count pad) or 11 matrix slots remain of room_u, room_m; returns
+// the op it stopped at (b if none).
+template <class R>
+__device__ int group_shape(const Ctx<R> &c, int a, int b, int room_u, int room_m, int &nu, int &nm)
+{
+    const ExecParams &P = c.P;
+    const lds<WgShared> &S = c.S;
+    uint32_t pend = 0;
+    nu = 0;
+    nm = 0;
+    int o = a;
+    for (; o < b; ++o) {
+        if (nu + 12 > room_u || nm + 11 > room_m) break;
+        const DevOp &op = op_at(c, o);
+        const int d = c.dec[o - S.start];
+        const double sc = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
+        if (op.kind == DK_BFUNC || ((op.flags & DF_COND) && d == kSkip)) continue;
+        switch (op.kind) {
+        case DK_MAT1:
+            pend |= 1u << op.rb[0];
+            break;
+        case DK_KRAUS: {
+            const DevRule &ru = rule_at(c, op.rule);
+            if (((ru.scalar_mask >> d) & 1u) && sc == 1.0) break;
+            pend |= 1u << op.rb[0];
+            break;
+        }
+        case DK_PAULI: {
+            const uint32_t code = pauli_code_c(c, op.rule, rule_at(c, op.rule), d);
+            for (int t = 0; t < op.nq; ++t)
+                if (((code >> t) | (code >> (8 + t))) & 1u) pend |= 1u << op.rb[t];
+            break;
+        }
+        default: {  // CX, CZ, SWAP: flush both bits, then the micro-op itself
+            const uint32_t f = pend & ((1u << op.rb[0]) | (1u << op.rb[1]));
+            nu += __builtin_popcount(f) + 1;
+            nm += __builtin_popcount(f);
+            pend &= ~f;
+        }
+        }
+    }
+    (void)P;
+    nu += __builtin_popcount(pend);
+    nm += __builtin_popcount(pend);
+    return o;
+}
+
 // Build the register groups and micro-ops of [S.start, S.end) with the
-// pass's decisions; may shorten the pass if LDS capacity runs out.
+// pass's decisions; may shorten the pass if LDS room runs out. Called by
+// every thread (the first wave does the work); ends with a barrier.
+//  1. Group boundaries: the static group changes between consecutive ops.
+//  2. Each lane counts its group's micro-ops and matrices; exclusive scans
+//     give every group its own micro-op and matrix range. The first group
+//     that does not fit is cut (or dropped) and ends the pass.
+//  3. Each lane fuses its group into its range and folds its trailing
+//     permutations.
 template <class R>
 __device__ __noinline__ void build_uops(Ctx<R> &c)
 {
     const ExecParams &P = c.P;
     lds<WgShared> &S = c.S;
-    int ng = 0, nu = 0, nm = 0;
-    uint64_t flops = 0;
-    int j = S.start;
-    bool cut = false;
+    const int tid = c.tid;
+    const int start = S.start, end0 = S.end;
+    constexpr int kMats = kPassMatBytes / (8 * (int)sizeof(R));
+    static_assert(kMaxPassGroups <= 64, "one lane of the first wave per group");
     // groups that run on two register sets (see two_sets): closing
     // permutations are folded into the stores, counts padded to even
-    const bool pairs = (1u << (P.tile_q - 8)) * sizeof(typename V2<R>::T) <= 256u;
-    while (j < S.end && !cut) {
-        const uint32_t g = op_at(c, j).group;
-        const GroupInfo &gi = P.groups[g];
-        const int a = j, b = min((int)gi.end_op, S.end);
-        if (ng >= kMaxPassGroups) { cut = true; S.end = j; break; }
-        if (gi.fallback) {
-            c.ug[ng].gidx = (int)g;
-            c.ug[ng].a = a;
-            c.ug[ng].b = b;
-            c.ug[ng].flags = kGrpFallback;
-            for (int o = a; o < b; ++o) flops += op_flops(P, op_at(c, o), c.dec[o - S.start]);
-            ++ng;
-            j = b;
-            continue;
-        }
-        const int first = nu;
-        uint32_t pend_set = 0;
-        int o = a;
-        for (; o < b; ++o) {
-            // room for this op (<= 3 micro-ops), the group's final flush (<= 8)
-            // and an even-count pad (1)
-            constexpr int kMats = kPassMatBytes / (8 * (int)sizeof(R));
-            if (nu + 12 > kMaxPassUops || nm + 11 > kMats) { cut = true; break; }
-            const DevOp &op = op_at(c, o);
-            const int d = c.dec[o - S.start];
-            const double sc = (o == S.start && S.pending >= 0) ? S.first_scale : 1.0;
-            if (op.kind == DK_BFUNC || ((op.flags & DF_COND) && d == kSkip)) continue;
-            switch (op.kind) {
-            case DK_MAT1:
-                fuse_factor(c, op.rb[0], op_matrix_at(c, o, op), 1.0, pend_set);
-                break;
-            case DK_KRAUS: {
-                const DevRule &ru = rule_at(c, op.rule);
-                // c * I: the state is kept unnormalised anyway
-                if (((ru.scalar_mask >> d) & 1u) && sc == 1.0) break;
-                fuse_factor(c, op.rb[0], P.pool + ru.mats + (size_t)d * 8, sc, pend_set);
+    const bool pairs = (1u << (P.tile_q - kWGBits)) * sizeof(typename V2<R>::T) <= 256u;
+    int ng = 0, end = end0;
+    if (tid < 64) {
+        for (int base = start; base < end0; base += 64) {
+            const int o = base + tid;
+            const bool in = o < end0;
+            const uint32_t g = in ? op_at(c, o).group : 0u;
+            const bool first = in && (o == start || op_at(c, o - 1).group != g);
+            const uint64_t mask = __ballot(first);
+            const int idx = ng + __popcll(mask & ((1ull << tid) - 1ull));
+            if (first && idx < kMaxPassGroups) {
+                c.ug[idx].gidx = (int)g;
+                c.ug[idx].a = o;
+            }
+            // the start of group kMaxPassGroups ends the pass
+            const uint64_t over = __ballot(first && idx == kMaxPassGroups);
+            ng += __popcll(mask);
+            if (over) {
+                end = __shfl(o, __ffsll((long long)over) - 1, 64);
+                ng = kMaxPassGroups;
                 break;
             }
-            case DK_PAULI: {
-                const uint32_t code = pauli_code_c(c, op.rule, rule_at(c, op.rule), d);
-                if (code == 0) break;  // identity
-                for (int t = 0; t < op.nq; ++t) {
-                    const uint32_t x = (code >> t) & 1u, z = (code >> (8 + t)) & 1u;
-                    if (!x && !z) continue;
-                    // X = [[0,1],[1,0]], Z = [[1,0],[0,-1]], Y = [[0,-i],[i,0]]
-                    double pm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                    if (x && !z) { pm[2] = 1; pm[4] = 1; }
-                    else if (!x && z) { pm[0] = 1; pm[6] = -1; }
-                    else { pm[3] = -1; pm[5] = 1; }
-                    fuse_factor(c, op.rb[t], pm, 1.0, pend_set);
-                }
-                break;
-            }
-            default: {  // CX, CZ, SWAP
-                fuse_flush(c, op.rb[0], pend_set, nu, nm, flops);
-                fuse_flush(c, op.rb[1], pend_set, nu, nm, flops);
-                UOp u;
-                u.kind = op.kind == DK_CX ? UK_CX : op.kind == DK_CZ ? UK_CZ : UK_SWAP;
-                u.j0 = op.rb[0];
-                u.j1 = op.rb[1];
-                u.code = 0;
-                u.mat = 0;
-                u.pad2 = 0;
-                put_uop(c.uops + nu++, u);
-            }
-            }
         }
-        for (int jj = 0; jj < 8; ++jj) fuse_flush(c, jj, pend_set, nu, nm, flops);
-        const uint32_t gflags = pairs ? fold_trailing_perms(c.uops, first, nu) : 0u;
-        c.ug[ng].gidx = (int)g;
-        c.ug[ng].a = first;
-        c.ug[ng].b = nu - first;
-        c.ug[ng].flags = gflags;
-        ++ng;
-        if (cut) {
-            S.end = o;
-            break;
-        }
-        j = b;
     }
-    if (cut) S.stop = STOP_NONE;
-    S.n_ug = ng;
-    S.pass_flops = flops;
-    S.st[ST_GROUPS] += ng;
-    S.st[ST_UOPS] += nu;
+    __syncthreads();
+    // the lane's group record, written once every lane has read the ranges
+    int rec_a = 0, rec_b = 0, rec_gidx = 0;
+    uint32_t rec_flags = 0;
+    if (tid < 64) {
+        const int g = tid;
+        int a = 0, b = 0, fb = 0, cu = 0, cm = 0;
+        if (g < ng) {
+            rec_gidx = c.ug[g].gidx;
+            a = c.ug[g].a;
+            b = g + 1 < ng ? c.ug[g + 1].a : end;
+            fb = P.groups[rec_gidx].fallback ? 1 : 0;
+            if (!fb) {
+                group_shape(c, a, b, 1 << 30, 1 << 30, cu, cm);
+                cu += 1;  // room for an even-count pad
+            }
+        }
+        // exclusive scans over the groups
+        int pu = cu, pm = cm;
+#pragma unroll
+        for (int s = 1; s < 64; s <<= 1) {
+            const int xu = __shfl_up(pu, s, 64), xm = __shfl_up(pm, s, 64);
+            if (tid >= s) {
+                pu += xu;
+                pm += xm;
+            }
+        }
+        pu -= cu;
+        pm -= cm;
+        const bool fits = g >= ng || (pu + cu <= kMaxPassUops && pm + cm <= kMats);
+        const uint64_t bad = __ballot(!fits);
+        bool cut = end != end0;
+        if (bad) {
+            // the first group that does not fit is cut where the room ends
+            const int gs = __ffsll((long long)bad) - 1;
+            int o = 0;
+            if (g == gs) {
+                o = group_shape(c, a, b, kMaxPassUops - pu, kMats - pm, cu, cm);
+                cu += 1;
+                b = o;
+            }
+            o = __shfl(o, gs, 64);
+            const int a_gs = __shfl(a, gs, 64);
+            ng = o > a_gs ? gs + 1 : gs;
+            end = o;
+            cut = true;
+        }
+        unsigned long long flops = 0;
+        int count = 0;
+        if (g < ng && fb) {
+            for (int o = a; o < b; ++o) flops += op_flops(P, op_at(c, o), c.dec[o - start]);
+            rec_a = a;
+            rec_b = b;
+            rec_flags = kGrpFallback;
+        } else if (g < ng) {
+            const int ul = pu + cu, ml = pm + cm;
+            int nu = pu, nm = pm;
+            uint64_t fl = 0;
+            PendRegs pr;
+            pr.set = 0;
+            for (int o = a; o < b; ++o) {
+                const DevOp &op = op_at(c, o);
+                const int d = c.dec[o - start];
+                const double sc = (o == start && S.pending >= 0) ? S.first_scale : 1.0;
+                if (op.kind == DK_BFUNC || ((op.flags & DF_COND) && d == kSkip)) continue;
+                switch (op.kind) {
+                case DK_MAT1:
+                    fuse_factor(pr, op.rb[0], op_matrix_at(c, o, op), 1.0);
+                    break;
+                case DK_KRAUS: {
+                    const DevRule &ru = rule_at(c, op.rule);
+                    // c * I: the state is kept unnormalised anyway
+                    if (((ru.scalar_mask >> d) & 1u) && sc == 1.0) break;
+                    fuse_factor(pr, op.rb[0], P.pool + ru.mats + (size_t)d * 8, sc);
+                    break;
+                }
+                case DK_PAULI: {
+                    const uint32_t code = pauli_code_c(c, op.rule, rule_at(c, op.rule), d);
+                    if (code == 0) break;  // identity
+                    for (int t = 0; t < op.nq; ++t) {
+                        const uint32_t x = (code >> t) & 1u, z = (code >> (8 + t)) & 1u;
+                        if (!x && !z) continue;
+                        // X = [[0,1],[1,0]], Z = [[1,0],[0,-1]], Y = [[0,-i],[i,0]]
+                        double pmat[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                        if (x && !z) { pmat[2] = 1; pmat[4] = 1; }
+                        else if (!x && z) { pmat[0] = 1; pmat[6] = -1; }
+                        else { pmat[3] = -1; pmat[5] = 1; }
+                        fuse_factor(pr, op.rb[t], pmat, 1.0);
+                    }
+                    break;
+                }
+                default: {  // CX, CZ, SWAP
+                    fuse_flush(c, pr, op.rb[0], nu, nm, ul, ml, fl);
+                    fuse_flush(c, pr, op.rb[1], nu, nm, ul, ml, fl);
+                    UOp u;
+                    u.kind = op.kind == DK_CX ? UK_CX : op.kind == DK_CZ ? UK_CZ : UK_SWAP;
+                    u.j0 = op.rb[0];
+                    u.j1 = op.rb[1];
+                    u.code = 0;
+                    u.mat = 0;
+                    u.pad2 = 0;
+                    if (nu < ul) put_uop(c.uops + nu, u);
+                    ++nu;
+                }
+                }
+            }
+            for (int jj = 0; jj < kMaxRegBits; ++jj) fuse_flush(c, pr, jj, nu, nm, ul, ml, fl);
+            if (nu + 1 > ul || nm > ml || (pr.set >> kMaxRegBits) != 0u) {
+                // the counts disagree with what was built: run nothing, report it
+                atomicOr(&P.ctl->error, kErrFuse);
+                nu = pu;
+            }
+            rec_flags = pairs ? fold_trailing_perms(c.uops, pu, nu) : 0u;
+            rec_a = pu;
+            rec_b = nu - pu;
+            count = nu - pu;
+            flops = fl;
+        }
+        // totals over the groups
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1) {
+            flops += __shfl_xor(flops, s, 64);
+            count += __shfl_xor(count, s, 64);
+        }
+        if (tid == 0) {
+            if (cut) {
+                S.end = end;
+                S.stop = STOP_NONE;
+            }
+            S.n_ug = ng;
+            S.pass_flops = flops;
+            S.st[ST_GROUPS] += ng;
+            S.st[ST_UOPS] += count;
+        }
+    }
+    __syncthreads();
+    if (tid < ng) {
+        c.ug[tid].gidx = rec_gidx;
+        c.ug[tid].a = rec_a;
+        c.ug[tid].b = rec_b;
+        c.ug[tid].flags = rec_flags;
+    }
+    __syncthreads();
 }
 
 // ----------------------------------------------------------- reductions
@@ -1644,14 +1789,18 @@ __device__ __noinline__ void reduce_tile(Ctx<R> &c, const DevOp &op, double (&ac
             default: reduce_kraus_dense<R, 5>(c, op.lb, K, nm, acc); break;
             }
         }
-    } else {  // DK_MEASURE
+    } else {  // DK_MEASURE: only the op's 2^nq outcomes are accumulated
+        const int no = 1 << op.nq;
         for (uint32_t i = c.tid; i < c.tsize; i += kWG) {
             uint32_t pat = 0;
             for (int t = 0; t < op.nq; ++t) pat |= ((i >> op.lb[t]) & 1u) << t;
             const double w = abs2d(L[c.at(i)]);
             acc[0] += w;
 #pragma unroll
-            for (int o = 0; o < 16; ++o) acc[1 + o] += (pat == (uint32_t)o) ? w : 0.0;
+            for (int o = 0; o < 16; ++o) {
+                if (o >= no) break;
+                acc[1 + o] += (pat == (uint32_t)o) ? w : 0.0;
+            }
         }
     }
 }
@@ -2260,6 +2409,20 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
         if (tid == 0) c.dec[0] = S.pending;
         ++j;
     }
+    if (m == 1) {
+        // one shot: its Pauli draws depend neither on each other nor on the
+        // state, so every op of the window is drawn at once, one per thread
+        // (a draw past where the pass stops is drawn again by the next pass)
+        const uint64_t shot = (uint64_t)P.shot_perm[S.lo];
+        const int jend = min(end_static, start + lim);
+        for (int q = j + tid; q < jend; q += kWG) {
+            const DevOp &o = op_at(c, q);
+            if (o.kind != DK_PAULI) continue;
+            const double u = philox_u01(P.seed, P.shot_base + shot, o.r, 0);
+            c.dec[q - start] = (int16_t)pauli_pick_c(c, o.rule, rule_at(c, o.rule), u);
+        }
+        __syncthreads();
+    }
     double nlb = S.norm_lb;
     int stop = STOP_NONE;
     const double lb_floor = sizeof(R) == 4 ? 0x1.0p-30 : 0x1.0p-200;
@@ -2267,8 +2430,8 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
         while (j < end_static && j - start < lim) {
             const DevOp &oj = op_at(c, j);
             const uint16_t kd = oj.kind;
-            if (kd == DK_PAULI || kd == DK_KRAUS || kd == DK_MEASURE || kd == DK_BFUNC ||
-                (oj.flags & DF_COND))
+            if ((kd == DK_PAULI && m != 1) || kd == DK_KRAUS || kd == DK_MEASURE ||
+                kd == DK_BFUNC || (oj.flags & DF_COND))
                 break;
             ++j;
         }
@@ -2298,14 +2461,13 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
         }
         const DevRule &ru = rule_at(c, op.rule);
         if (m == 1) {
-            // every thread evaluates the single shot's draw (no barrier)
-            const uint64_t shot = (uint64_t)P.shot_perm[S.lo];
-            const double u = philox_u01(P.seed, P.shot_base + shot, op.r, 0);
-            if (op.kind == DK_PAULI) {
-                if (tid == 0) c.dec[j - start] = pauli_pick_c(c, op.rule, ru, u);
+            if (op.kind == DK_PAULI) {  // drawn above
                 ++j;
                 continue;
             }
+            // every thread evaluates the single shot's draw (no barrier)
+            const uint64_t shot = (uint64_t)P.shot_perm[S.lo];
+            const double u = philox_u01(P.seed, P.shot_base + shot, op.r, 0);
             if (u < ru.lam_min0 && nlb * ru.lam_min0 >= lb_floor) {
                 if (tid == 0) c.dec[j - start] = 0;
                 if (!(ru.scalar_mask & 1u)) nlb *= ru.lam_min0;
@@ -2366,9 +2528,9 @@ __device__ __noinline__ void plan_pass(Ctx<R> &c)
         S.norm_lb = nlb;
         S.n_ug = 0;
         S.pass_flops = 0;
-        if (P.use_groups && j > start) build_uops(c);
     }
     __syncthreads();
+    if (P.use_groups && j > start) build_uops(c);  // ends with a barrier
 }
 
 template <class R>
@@ -2876,7 +3038,6 @@ exec_kernel(ExecParams P)
     c.ug = (lds<UGroup> *)uarea;
     c.uops = (lds<UOp> *)(uarea + kMaxPassGroups * sizeof(UGroup));
     c.mats = (lds<R> *)((lds<unsigned char> *)c.uops + kMaxPassUops * sizeof(UOp));
-    c.pend = (lds<double> *)((lds<unsigned char> *)c.mats + kPassMatBytes);
     {
         // op staging area after the per-workgroup state
         lds<unsigned char> *st = (lds<unsigned char> *)&S + shared_bytes16();
@@ -3102,7 +3263,7 @@ __global__ void restart_kernel(ExecParams P, int n_wait)
 static size_t uarea_bytes(int cnt_in_tile)
 {
     const size_t fuse = svb::kMaxPassGroups * sizeof(svb::UGroup) + svb::kMaxPassUops * sizeof(svb::UOp) +
-                        svb::kPassMatBytes + 8 * 8 * sizeof(double);
+                        svb::kPassMatBytes;
     const size_t cnt = 16 * svb::kWG * 4;  // split counters, unless they fit in the tile
     return (!cnt_in_tile && cnt > fuse) ? cnt : fuse;
 }

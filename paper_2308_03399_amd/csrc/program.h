@@ -7,6 +7,8 @@
 namespace svb {
 
 constexpr int kWG = 256;             // threads per executor workgroup
+constexpr int kWGBits = 8;           // log2(kWG)
+static_assert((1 << kWGBits) == kWG, "kWGBits is log2(kWG)");
 constexpr int kMaxPassOps = 512;     // ops applied in one tile sweep
 constexpr int kMaxPassGroups = 64;   // register groups in one sweep
 constexpr int kMaxPassUops = 384;    // register micro-ops in one sweep
@@ -139,6 +141,7 @@ constexpr uint32_t kErrTimeout = 1;
 constexpr uint32_t kErrQueue = 2;
 constexpr uint32_t kErrLock = 4;
 constexpr uint32_t kErrState = 8;
+constexpr uint32_t kErrFuse = 16;   // plan-time fusion overran its counted room (internal)
 
 struct ExecParams {
     const DevOp *ops;

@@ -188,7 +188,7 @@ static sv_status derive(sv_batch *b)
     // when its passes can be staged in LDS (states of at most 32 KiB) or
     // when asked for (engine 2); larger resident states run their ops as
     // LDS sweeps by default, which measured faster without staging
-    const int r = b->tile_q - 8;
+    const int r = b->tile_q - kWGBits;
     const bool small = state_bytes(b) <= (32u << 10);
     const bool r_ok = b->resident ? (r >= 2 && r <= 5 && (b->opt_engine == 2 || small))
                                   : (b->dtype == SV_C128 ? (r == 4 || r == 5) : (r >= 4 && r <= 6));
