@@ -372,10 +372,12 @@ struct Ctx {
     uint32_t swm;      // swizzle mask of the current pass (0: identity)
     int k;
     int tid;
-    // LDS position of tile index i: low six bits mixed with bits 6..17
+    // LDS position of tile index i: bits 6+j and 7+j are added (XOR) to
+    // bit j of the low six, for j in swm. Bits 6 and up stay, so the map is
+    // its own inverse, and it is linear over GF(2)
     __device__ __forceinline__ uint32_t at(uint32_t i) const
     {
-        return i ^ (((i >> 6) ^ (i >> 12)) & swm);
+        return i ^ (((i >> 6) ^ (i >> 7)) & swm);
     }
 };
 
@@ -1067,7 +1069,7 @@ struct Hot {
     int n_ug, k, tid;
     __device__ __forceinline__ uint32_t at(uint32_t i) const
     {
-        return i ^ (((i >> 6) ^ (i >> 12)) & swm);
+        return i ^ (((i >> 6) ^ (i >> 7)) & swm);
     }
 };
 

@@ -551,11 +551,12 @@ static uint32_t qmask_of(const XOp &x)
 }
 
 // effect of tile bit b on the low six bits of its swizzled LDS position
+// (the executor's swizzle adds bits 6+j and 7+j to bit j, for j in swz)
 static uint32_t fold_vec(int b, uint32_t swz)
 {
     if (b < 6) return 1u << b;
-    if (b < 12) return (1u << (b - 6)) & swz;
-    return (1u << (b - 12)) & swz;
+    const uint32_t i = 1u << b;
+    return ((i >> 6) ^ (i >> 7)) & swz & 63u;
 }
 
 static int gf2_rank_add(uint32_t basis[6], uint32_t v)
@@ -590,7 +591,7 @@ static size_t unit_end(const std::vector<XOp> &xo, const std::vector<uint32_t> &
     return e;
 }
 
-static void plan_program(int n, int k, int r, bool resident, bool use_groups, uint32_t swz,
+static void plan_program(int n, int k, int r, bool resident, bool use_groups, uint32_t swz, int span,
                          const std::vector<XOp> &xo, const std::vector<Rule> &rules,
                          bool terminal, Plan &P)
 {
@@ -669,22 +670,39 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
             gi.first_op = (uint32_t)P.order.size();
             gi.fallback = fb_group ? 1u : 0u;
             if (!fb_group && use_groups) {
-                // register bits: the group's tile bits, then padding; lanes:
-                // tile bits whose swizzled positions spread over the banks
+                // register bits: the group's tile bits, then padding. Lanes:
+                // the lanes that one LDS cycle serves hit distinct banks when
+                // their thread bits map to independent vectors in the low
+                // bits of the swizzled amplitude index. Measured on gfx950
+                // for 8-byte accesses: a write cycle serves 16 lanes (thread
+                // bits 0..3 should span index bits 0..3), a read cycle 32
+                // (thread bits 0..4, index bits 0..4). So thread bits
+                // 0..span-2 are chosen first, then bit span-1; taking
+                // independent vectors greedily reaches the largest rank at
+                // each stage (a matroid). The other thread bits take what
+                // is left
                 uint32_t reg_tile = 0;
                 for (int q = 0; q < n; ++q)
                     if ((G >> q) & 1) reg_tile |= 1u << lbit[q];
                 std::vector<int> cand;
                 for (int b = 0; b < k; ++b)
                     if (!((reg_tile >> b) & 1)) cand.push_back(b);
-                uint32_t basis[6] = {0, 0, 0, 0, 0, 0};
                 std::vector<int> lanes, others;
-                for (int b : cand) {
-                    if ((int)lanes.size() < 6 && gf2_rank_add(basis, fold_vec(b, swz)))
-                        lanes.push_back(b);
-                    else
-                        others.push_back(b);
+                uint32_t taken = 0;
+                for (int want = span - 1; want <= span; ++want) {
+                    const uint32_t low = (1u << want) - 1u;
+                    uint32_t basis[6] = {0, 0, 0, 0, 0, 0};
+                    for (int b : lanes) gf2_rank_add(basis, fold_vec(b, swz) & low);
+                    for (int b : cand) {
+                        if ((int)lanes.size() >= want) break;
+                        if (!((taken >> b) & 1u) && gf2_rank_add(basis, fold_vec(b, swz) & low)) {
+                            lanes.push_back(b);
+                            taken |= 1u << b;
+                        }
+                    }
                 }
+                for (int b : cand)
+                    if (!((taken >> b) & 1u)) others.push_back(b);
                 // padding of the register bits comes from bits not used as lanes
                 std::vector<int> regs;
                 for (int b = 0; b < k; ++b)
@@ -1156,7 +1174,7 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     } else {
         // a resident state is stored unswizzled
         plan_program(n, b->tile_q, b->reg_bits, b->resident != 0, b->use_groups != 0,
-                     b->resident ? 0u : swz, xo, rules, terminal, plan);
+                     b->resident ? 0u : swz, b->dtype == SV_C128 ? 4 : 5, xo, rules, terminal, plan);
     }
     const std::vector<PassInfo> &passes = plan.passes;
     std::vector<double> pool;
@@ -1611,7 +1629,7 @@ sv_status svb_debug_plan(int n_qubits, int tile_q, int reg_bits, const sv_op *op
     const bool resident = n_qubits <= tile_q;
     Plan plan;
     plan_program(n_qubits, resident ? n_qubits : tile_q, reg_bits, resident, reg_bits > 0,
-                 resident ? 0u : 62u, xo, rules, terminal, plan);
+                 resident ? 0u : 62u, 5, xo, rules, terminal, plan);
     *n_out = plan.order.size();
     *n_passes = plan.passes.size();
     *n_groups = plan.groups.size();
