@@ -58,7 +58,7 @@ def progress(msg: str):
 def kernel_source_hash() -> str:
     """Hash of the executor's source and of the build script (its flags)."""
     h = hashlib.sha256()
-    for f in ("csrc/kernels.hip", "csrc/program.h", "build.py"):
+    for f in ("csrc/kernels.hip", "csrc/kernels_mfma.hip", "csrc/program.h", "build.py"):
         with open(os.path.join(ROOT, "paper_2308_03399_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

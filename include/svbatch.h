@@ -166,6 +166,9 @@ typedef struct {
                                   graph (option "graph"), else 0                   */
     uint32_t program_uploads;  /* 1 if the op program was copied to the device
                                   (0: unchanged since the last graph run)          */
+    uint32_t mfma;             /* 1 if fused one-qubit micro-ops of complex64
+                                  register groups ran on the matrix cores
+                                  (option "mfma")                                  */
 } sv_stats;
 
 /* Create a handle for n_qubits (1..30) and n_shots (>= 1) in the given
@@ -208,6 +211,10 @@ sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
  *   "spin_elapsed" 1: the bound above counts from the start of each wait,
  *                  whatever the other workgroups do (forces the failure
  *                  path from the host in tests); 0 (default): watchdog
+ *   "mfma"         complex64 fused one-qubit micro-ops: 0 automatic (on the
+ *                  matrix cores when the circuit's register groups average
+ *                  four or more one-qubit gates), 1 vector ALU, 2 matrix
+ *                  cores. Results differ only by rounding
  *   "graph"        1: a run's two launches (initialisation, then the
  *                  persistent executor) are kept as a HIP graph on the handle;
  *                  later runs update the launch arguments (seed, shot offset,

@@ -88,7 +88,8 @@ class sv_stats(ctypes.Structure):
                 ("exec_ms", ctypes.c_double), ("exec_launches", ctypes.c_uint32),
                 ("tile_buffers", ctypes.c_uint32), ("groups", ctypes.c_uint64),
                 ("uops", ctypes.c_uint64), ("near_ties", ctypes.c_uint64),
-                ("graph_replays", ctypes.c_uint32), ("program_uploads", ctypes.c_uint32)]
+                ("graph_replays", ctypes.c_uint32), ("program_uploads", ctypes.c_uint32),
+                ("mfma", ctypes.c_uint32)]
 
     def as_dict(self) -> Dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -14,7 +14,9 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libsvbatch.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["runtime.cpp", "kernels.hip", "counts.hip", "plain.hip", "noalloc.hip"]
+SOURCES = ["runtime.cpp", "kernels.hip", "kernels_mfma.hip", "counts.hip", "plain.hip", "noalloc.hip"]
+# executor translation units (resource-usage remarks, no VGPR spills into AGPRs)
+EXEC_SOURCES = ("kernels.hip", "kernels_mfma.hip")
 ARCH = os.environ.get("SVB_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed-FP32 instructions in device code
@@ -27,9 +29,12 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 EXEC_FLAGS = ["-mllvm", "-amdgpu-spill-vgpr-to-agpr=0",
               "-Rpass-analysis=kernel-resource-usage"]
 # executor instantiations that must run two workgroups per compute unit
-# (complex64 at 16 and 32 amplitudes per thread, complex128 at 16)
+# (complex64 at 16 and 32 amplitudes per thread, in both one-qubit forms,
+# complex128 at 16)
 TWO_WAVE_KERNELS = ["_ZN3svb11exec_kernelIfLi32EEEvNS_10ExecParamsE",
                     "_ZN3svb11exec_kernelIfLi16EEEvNS_10ExecParamsE",
+                    "_ZN3svb16exec_kernel_mfmaIfLi32EEEvNS_10ExecParamsE",
+                    "_ZN3svb16exec_kernel_mfmaIfLi16EEEvNS_10ExecParamsE",
                     "_ZN3svb11exec_kernelIdLi16EEEvNS_10ExecParamsE"]
 RESOURCES = os.path.join(OUT_DIR, "kernel_resources.json")
 
@@ -56,7 +61,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(BUILD_DIR, src + ".o")
         objs.append(obj)
-        extra = EXEC_FLAGS if src == "kernels.hip" else []
+        extra = EXEC_FLAGS if src in EXEC_SOURCES else []
         cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -67,8 +72,8 @@ def build(verbose: bool = False) -> str:
     for src, p in procs:
         out, _ = p.communicate()
         raw = out.decode(errors="replace")
-        if src == "kernels.hip":
-            resources = parse_resource_usage(raw)
+        if src in EXEC_SOURCES:
+            resources.update(parse_resource_usage(raw))
         text = "\n".join(l for l in raw.splitlines()
                          if "packed-fp32-ops" not in l and "remark:" not in l
                          and "Rpass" not in l)

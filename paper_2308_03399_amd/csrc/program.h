@@ -190,6 +190,8 @@ struct ExecParams {
                              // one-qubit matrices are copied to LDS before it is planned
     int32_t n_rules;         // noise rules of the program
     int32_t stage_rules;     // 1: the rules and their Pauli tables are copied to LDS once
+    int32_t mfma1;           // 1: fused non-diagonal one-qubit micro-ops of complex64
+                             // register groups run on the matrix cores
 };
 
 }  // namespace svb
