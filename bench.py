@@ -534,7 +534,7 @@ def main():
         roof = {"bound": "alu", "achieved": round(tfs, 3), "peak": alu_peak,
                 "unit": "TFLOP/s", "frac": round(frac_alu, 4)}
     roof["traffic"] = traffic
-    roof["kernel"] = "svb::exec_kernel"
+    roof["kernel"] = "svb::exec_kernel_mfma" if stats[0]["mfma"] else "svb::exec_kernel"
     roof["launch_ms"] = round(exec_ms / max(launches, 1), 3)
     roof["algorithmic_bytes_per_launch"] = int(amp_bytes / max(launches, 1))
     roof["algorithmic_flops_per_launch"] = int(flops / max(launches, 1))
@@ -567,6 +567,7 @@ def main():
             "passes_per_shot": round(sum(s["passes"] for s in stats) / total_shots, 2),
             "graph_replays": sum(s["graph_replays"] for s in stats),
             "program_uploads": sum(s["program_uploads"] for s in stats),
+            "one_qubit_form": "matrix cores" if stats[0]["mfma"] else "vector ALU",
         },
         "roofline": roof,
     }
