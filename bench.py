@@ -64,10 +64,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, dtype: str, shots_per_step: int, mode: str):
+def measured_traffic(workload: str, dtype: str, shots_per_step: int, mode: str,
+                     alg_bytes: int):
     """HBM bytes per executor launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source, in the same mode
-    and with the same shots per launch."""
+    summary, if it was taken on the current kernel source, in the same mode,
+    with the same shots per launch and the same pass plan (its algorithmic
+    bytes per launch equal this launch's)."""
     path = os.path.join(ROOT, "profiles", f"exec_kernel_{workload}_{dtype}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -76,6 +78,8 @@ def measured_traffic(workload: str, dtype: str, shots_per_step: int, mode: str):
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
     if int(t.get("shots_per_launch", -1)) != shots_per_step or t.get("mode", "batch") != mode:
+        return None
+    if int(t.get("algorithmic_bytes_per_launch", -1)) != int(alg_bytes):
         return None
     return float(t["hbm_bytes_per_launch"])
 
@@ -526,7 +530,8 @@ def main():
     alu_peak = FP32_VECTOR_PEAK_TF if args.dtype == "c64" else FP64_VECTOR_PEAK_TF
     frac_hbm = gbs / HBM_PEAK_GBS
     frac_alu = tfs / alu_peak
-    traffic = measured_traffic(args.workload, args.dtype, B, args.mode)
+    traffic = measured_traffic(args.workload, args.dtype, B, args.mode,
+                               int(amp_bytes / max(launches, 1)))
     if frac_hbm >= frac_alu:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(frac_hbm, 4)}

@@ -86,6 +86,21 @@ static hipError_t ev_ms(float *ms, hipEvent_t a, hipEvent_t b)
 constexpr int kPlainRedBlocks = 1024;  // blocks of a plain-mode reduction
 
 // ------------------------------------------------------------------ handle
+struct Plan {
+    std::vector<uint32_t> order;  // device position -> expanded index
+    std::vector<PassInfo> passes;
+    std::vector<GroupInfo> groups;
+    std::vector<uint32_t> op_pass, op_group;  // per device position
+};
+
+// The pass plan of the last circuit run on a handle, with the structural
+// signature it was made from (planning depends on nothing else).
+struct PlanCache {
+    std::vector<int32_t> sig;
+    Plan plan;
+    bool valid = false;
+};
+
 struct sv_batch {
     int n = 0;
     int64_t shots = 0;
@@ -112,6 +127,7 @@ struct sv_batch {
     bool no_counts = false;            // no room reserved for the counts histogram
     int64_t opt_graph = 0;             // 1: launches replayed from a HIP graph
     int64_t opt_mfma = 0;              // 0 automatic, 1 vector ALU, 2 matrix cores
+    PlanCache plan_cache;              // reused while the circuit's structure repeats
     int mfma = 0;                      // the last program's choice
     bool noalloc_run = false;          // inside sv_run_circuit_noalloc
     hipGraph_t graph = nullptr;        // [init kernel] -> [executor]
@@ -517,12 +533,7 @@ static sv_status validate_and_expand(const sv_batch *b, const sv_op *ops, size_t
 // thread) register bits. Measures and dense 4x4 ops form groups of their own
 // that run as LDS sweeps. The final measurement of all qubits gets a pass of
 // its own with tile qubits 0..k-1 (contiguous chunks for sampling).
-struct Plan {
-    std::vector<uint32_t> order;  // device position -> expanded index
-    std::vector<PassInfo> passes;
-    std::vector<GroupInfo> groups;
-    std::vector<uint32_t> op_pass, op_group;  // per device position
-};
+
 
 // Ops whose effect depends on, or changes, per-shot state beyond their qubits:
 // Kraus channels and measurements (outcome probabilities), conditional ops
@@ -592,6 +603,9 @@ static size_t unit_end(const std::vector<XOp> &xo, const std::vector<uint32_t> &
     }
     return e;
 }
+
+// Tile sets tried per pass of a streamed state, besides the greedy one
+constexpr int kPassCandidates = 200;
 
 static void plan_program(int n, int k, int r, bool resident, bool use_groups, uint32_t swz, int span,
                          const std::vector<XOp> &xo, const std::vector<Rule> &rules,
@@ -738,9 +752,15 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
         P.passes.push_back(pi);
     };
 
-    while (!remaining.empty()) {
-        std::vector<uint32_t> sel, rest;
-        uint32_t T = base_mask, blocked = 0;
+    // One pass over the remaining ops, in list order: a unit (a gate and its
+    // channels) is taken when no earlier deferred unit shares a qubit with
+    // it (nor, for ordered ops, comes before it) and it fits the tile set.
+    // With fixed == 0 the tile set grows from base_mask as units are taken
+    // (greedy); otherwise it is `fixed`.
+    auto take = [&](uint32_t fixed, std::vector<uint32_t> &sel, std::vector<uint32_t> &rest) {
+        sel.clear();
+        rest.clear();
+        uint32_t T = fixed ? fixed : base_mask, blocked = 0;
         bool ord_blocked = false;
         for (size_t idx = 0; idx < remaining.size();) {
             const size_t e = unit_end(xo, remaining, idx, rules, false, r);
@@ -754,8 +774,8 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
                 m |= qmask_of(xo[remaining[t]]);
                 ord = ord || op_ordered(xo[remaining[t]]);
             }
-            const bool ok = !(m & blocked) && !(ord && ord_blocked) &&
-                            __builtin_popcount(T | m) <= k;
+            const bool fits = fixed ? !(m & ~fixed) : __builtin_popcount(T | m) <= k;
+            const bool ok = !(m & blocked) && !(ord && ord_blocked) && fits;
             for (size_t t = idx; t < e; ++t) (ok ? sel : rest).push_back(remaining[t]);
             if (ok) {
                 T |= m;
@@ -764,6 +784,90 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
                 ord_blocked |= ord;
             }
             idx = e;
+        }
+        return T;
+    };
+    // Streamed states: besides the greedy tile set, try fixed sets made of
+    // the qubits in order of first use among the next units, and seeded
+    // perturbations of that order, and keep the set that takes the most
+    // ops (fewer passes over the state). Deterministic for a circuit.
+    const bool search = !resident && n > k;
+    uint64_t rng = 0x9e3779b97f4a7c15ull;
+    auto next_rand = [&rng]() {
+        // splitmix64
+        uint64_t z = (rng += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return z ^ (z >> 31);
+    };
+    std::vector<uint32_t> um, ulen;   // units of the remaining list: qubit mask, op count
+    std::vector<uint8_t> uord;        // unit holds an ordered op
+    auto count_fixed = [&](uint32_t C) {
+        uint32_t blocked = 0;
+        bool ord_blocked = false;
+        size_t taken = 0;
+        for (size_t u = 0; u < um.size(); ++u) {
+            if (taken + ulen[u] > (size_t)kMaxPassOps) break;
+            if (!(um[u] & blocked) && !(uord[u] && ord_blocked) && !(um[u] & ~C)) {
+                taken += ulen[u];
+            } else {
+                blocked |= um[u];
+                ord_blocked = ord_blocked || uord[u];
+            }
+        }
+        return taken;
+    };
+    while (!remaining.empty()) {
+        std::vector<uint32_t> sel, rest;
+        uint32_t T = take(0, sel, rest);
+        if (search && !rest.empty()) {
+            um.clear();
+            ulen.clear();
+            uord.clear();
+            for (size_t idx = 0; idx < remaining.size();) {
+                const size_t e = unit_end(xo, remaining, idx, rules, false, r);
+                uint32_t m = 0;
+                bool ord = false;
+                for (size_t t = idx; t < e; ++t) {
+                    m |= qmask_of(xo[remaining[t]]);
+                    ord = ord || op_ordered(xo[remaining[t]]);
+                }
+                um.push_back(m);
+                ulen.push_back((uint32_t)(e - idx));
+                uord.push_back(ord ? 1 : 0);
+                idx = e;
+            }
+            std::vector<int> order;
+            uint32_t seen = base_mask;
+            for (size_t u = 0; u < um.size() && u < 256; ++u)
+                for (int q = 0; q < n; ++q)
+                    if (((um[u] & ~seen) >> q) & 1u) {
+                        order.push_back(q);
+                        seen |= 1u << q;
+                    }
+            for (int q = 0; q < n; ++q)
+                if (!((seen >> q) & 1u)) order.push_back(q);
+            const int free_q = k - __builtin_popcount(base_mask);
+            size_t best = sel.size();
+            uint32_t best_c = 0;
+            for (int cand = 0; cand <= kPassCandidates; ++cand) {
+                std::vector<int> o2 = order;
+                if (cand > 0) {
+                    const int swaps = (int)(next_rand() % 5);
+                    for (int t = 0; t < swaps; ++t) {
+                        const size_t i = next_rand() % o2.size(), j = next_rand() % o2.size();
+                        std::swap(o2[i], o2[j]);
+                    }
+                }
+                uint32_t C = base_mask;
+                for (int t = 0; t < free_q && t < (int)o2.size(); ++t) C |= 1u << o2[t];
+                const size_t got = count_fixed(C);
+                if (got > best) {
+                    best = got;
+                    best_c = C;
+                }
+            }
+            if (best_c) T = take(best_c, sel, rest);
         }
         emit_pass(sel, T);
         remaining.swap(rest);
@@ -1178,9 +1282,32 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
         plan.passes.push_back(pi);
         plan.groups.push_back(gi);
     } else {
-        // a resident state is stored unswizzled
-        plan_program(n, b->tile_q, b->reg_bits, b->resident != 0, b->use_groups != 0,
-                     b->resident ? 0u : swz, b->dtype == SV_C128 ? 4 : 5, xo, rules, terminal, plan);
+        // a resident state is stored unswizzled. The plan depends only on the
+        // ops' kinds, qubits, conditions and rule shapes and on the launch
+        // shape, so a run that repeats them (waves of one job, serving
+        // chunks) reuses the last plan
+        const uint32_t pswz = b->resident ? 0u : swz;
+        const int span = b->dtype == SV_C128 ? 4 : 5;
+        std::vector<int32_t> sig = {n, b->tile_q, b->reg_bits, b->resident, b->use_groups,
+                                    (int32_t)pswz, span, terminal ? 1 : 0, (int32_t)xo.size()};
+        sig.reserve(sig.size() + xo.size() * 8);
+        for (const XOp &x : xo) {
+            sig.push_back(x.kind);
+            sig.push_back(x.rule >= 0 ? (rules[x.rule].kraus ? 2 : 1) * 64 + rules[x.rule].nq : -1);
+            sig.push_back(x.cond_mask != 0 ? 1 : 0);
+            sig.push_back((int32_t)x.q.size());
+            for (int q : x.q) sig.push_back(q);
+        }
+        PlanCache &pc = b->plan_cache;
+        if (pc.valid && pc.sig == sig) {
+            plan = pc.plan;
+        } else {
+            plan_program(n, b->tile_q, b->reg_bits, b->resident != 0, b->use_groups != 0, pswz, span, xo,
+                         rules, terminal, plan);
+            pc.sig.swap(sig);
+            pc.plan = plan;
+            pc.valid = true;
+        }
     }
     const std::vector<PassInfo> &passes = plan.passes;
     std::vector<double> pool;
