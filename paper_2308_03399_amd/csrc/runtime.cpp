@@ -604,8 +604,10 @@ static size_t unit_end(const std::vector<XOp> &xo, const std::vector<uint32_t> &
     return e;
 }
 
-// Tile sets tried per pass of a streamed state, besides the greedy one
+// Tile sets tried per pass of a streamed state, besides the greedy one, and
+// rounds of single-qubit exchanges from the best of them
 constexpr int kPassCandidates = 200;
+constexpr int kPassExchangeRounds = 4;
 
 static void plan_program(int n, int k, int r, bool resident, bool use_groups, uint32_t swz, int span,
                          const std::vector<XOp> &xo, const std::vector<Rule> &rules,
@@ -866,6 +868,26 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
                     best = got;
                     best_c = C;
                 }
+            }
+            // then exchange one tile qubit for one outside while that helps
+            for (int round = 0; round < kPassExchangeRounds && best_c; ++round) {
+                uint32_t step_c = 0;
+                size_t step_best = best;
+                for (int a = 0; a < n; ++a) {
+                    if (!((best_c >> a) & 1u) || ((base_mask >> a) & 1u)) continue;
+                    for (int q = 0; q < n; ++q) {
+                        if ((best_c >> q) & 1u) continue;
+                        const uint32_t C = (best_c & ~(1u << a)) | (1u << q);
+                        const size_t got = count_fixed(C);
+                        if (got > step_best) {
+                            step_best = got;
+                            step_c = C;
+                        }
+                    }
+                }
+                if (!step_c) break;
+                best = step_best;
+                best_c = step_c;
             }
             if (best_c) T = take(best_c, sel, rest);
         }
