@@ -250,3 +250,28 @@ def test_random_keying_with_64_bit_seed_and_shot_ids(mode, n, tile):
     got = gpu_run(circ, noise, shots, dtype="c128", mode=mode, seed=seed, shot_offset=base, **opts)
     exp = oracle_memory(circ, noise, range(base, base + shots), seed=seed)
     assert mismatches(got["memory"], exp) == 0
+
+
+@pytest.mark.parametrize("mode", ["batch", "branch"])
+def test_plan_reuse_across_circuits_on_one_handle(mode):
+    # a handle keeps the last circuit's pass plan while the circuit's
+    # structure repeats; a different structure must plan afresh, and the
+    # same structure with other angles must reuse the plan correctly
+    import paper_2308_03399_amd as S
+    n, shots = 15, 64
+    noise = _noise_full()
+    a = W.random_layered(n, 4, seed=31, mid_measure=(2, (1, 7)))
+    b = W.random_small(n, 80, seed=32, n_mid=2)
+    a2 = W.random_layered(n, 4, seed=31, mid_measure=(2, (1, 7)))
+    for op in a2["ops"]:  # same structure, other angles
+        if op["kind"] == "u3":
+            op["params"] = [p + 0.25 for p in op["params"]]
+    sim = S.Simulator(n, shots, dtype="c128", mode=mode, tile_qubits=13, spin_limit_ms=60000)
+    try:
+        for name, circ, seed in (("A", a, 4), ("B", b, 5), ("A", a, 6), ("A'", a2, 7)):
+            say(f"case plan reuse mode={mode} circuit {name} seed {seed}")
+            sim.run(circ, noise, seed=seed)
+            got = sim.memory()
+            assert mismatches(got, oracle_memory(circ, noise, shots, seed=seed)) == 0, name
+    finally:
+        sim.close()
