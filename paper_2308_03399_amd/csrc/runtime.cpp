@@ -14,6 +14,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -93,13 +95,38 @@ struct Plan {
     std::vector<uint32_t> op_pass, op_group;  // per device position
 };
 
-// The pass plan of the last circuit run on a handle, with the structural
-// signature it was made from (planning depends on nothing else).
-struct PlanCache {
+// Pass plans of recent circuits, keyed by the structural signature each was
+// made from (planning depends on nothing else), shared by every handle of
+// the process: a job run as waves or serving chunks on fresh handles plans
+// once. At most kPlanCacheEntries, least recently used dropped first.
+struct PlanEntry {
     std::vector<int32_t> sig;
     Plan plan;
-    bool valid = false;
 };
+constexpr size_t kPlanCacheEntries = 8;
+static std::mutex g_plan_mu;
+static std::list<PlanEntry> g_plans;  // most recently used first
+
+static bool plan_lookup(const std::vector<int32_t> &sig, Plan &out)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
+        if (it->sig != sig) continue;
+        out = it->plan;
+        g_plans.splice(g_plans.begin(), g_plans, it);
+        return true;
+    }
+    return false;
+}
+
+static void plan_store(std::vector<int32_t> &&sig, const Plan &plan)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (const PlanEntry &e : g_plans)
+        if (e.sig == sig) return;
+    g_plans.push_front(PlanEntry{std::move(sig), plan});
+    if (g_plans.size() > kPlanCacheEntries) g_plans.pop_back();
+}
 
 struct sv_batch {
     int n = 0;
@@ -127,7 +154,6 @@ struct sv_batch {
     bool no_counts = false;            // no room reserved for the counts histogram
     int64_t opt_graph = 0;             // 1: launches replayed from a HIP graph
     int64_t opt_mfma = 0;              // 0 automatic, 1 vector ALU, 2 matrix cores
-    PlanCache plan_cache;              // reused while the circuit's structure repeats
     int mfma = 0;                      // the last program's choice
     bool noalloc_run = false;          // inside sv_run_circuit_noalloc
     hipGraph_t graph = nullptr;        // [init kernel] -> [executor]
@@ -1307,7 +1333,7 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
         // a resident state is stored unswizzled. The plan depends only on the
         // ops' kinds, qubits, conditions and rule shapes and on the launch
         // shape, so a run that repeats them (waves of one job, serving
-        // chunks) reuses the last plan
+        // chunks) reuses a cached plan
         const uint32_t pswz = b->resident ? 0u : swz;
         const int span = b->dtype == SV_C128 ? 4 : 5;
         std::vector<int32_t> sig = {n, b->tile_q, b->reg_bits, b->resident, b->use_groups,
@@ -1320,15 +1346,10 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
             sig.push_back((int32_t)x.q.size());
             for (int q : x.q) sig.push_back(q);
         }
-        PlanCache &pc = b->plan_cache;
-        if (pc.valid && pc.sig == sig) {
-            plan = pc.plan;
-        } else {
+        if (!plan_lookup(sig, plan)) {
             plan_program(n, b->tile_q, b->reg_bits, b->resident != 0, b->use_groups != 0, pswz, span, xo,
                          rules, terminal, plan);
-            pc.sig.swap(sig);
-            pc.plan = plan;
-            pc.valid = true;
+            plan_store(std::move(sig), plan);
         }
     }
     const std::vector<PassInfo> &passes = plan.passes;
