@@ -456,9 +456,9 @@ def main():
         # is ~10 min of host time)
         args.no_c128 = args.no_branch = args.no_cpu_baseline = True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: shots shard across GPUs by "
-              "shot-id range with no exchange, which this build does not "
-              "launch; use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: shots would shard across GPUs "
+              "by shot-id range with no exchange, and the library launches "
+              "on one device; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
