@@ -10,6 +10,8 @@ result:
   2, where the next tile is fetched while the current one computes.
 * workgroups: one or two per compute unit. This sets the number of shots
   each workgroup serves in batch mode.
+* complex64 only: the form of the fused one-qubit products (option mfma):
+  vector ALU or matrix cores. It is probed on the fastest launch shape.
 
 Every candidate runs a probe of the caller's circuit on a few waves of
 shots. The fastest per-shot executor time wins. Results are cached in a
@@ -107,15 +109,31 @@ def tune(circuit: Dict, noise: Optional[Dict], dtype: str = "c64", mode: str = "
         ms = st["exec_ms"] / shots
         rec = {"options": opts, "tile_qubits": st["tile_qubits"],
                "tile_buffers": st["tile_buffers"], "workers": st["workers"],
-               "ms_per_shot": ms}
+               "mfma": st["mfma"], "ms_per_shot": ms}
         probes.append(rec)
         if verbose:
             print(f"[autotune] {rec}", flush=True)
         if best is None or ms < best["ms_per_shot"]:
             best = rec
+    if dtype == "c64" and not _resident(circuit["n_qubits"], dtype):
+        # the one-qubit form on the fastest shape: both explicit choices
+        for mf in (1, 2):
+            opts = dict(best["options"], mfma=mf)
+            shots = waves * int(opts.get("workers", 2 * cus))
+            _probe(circuit, noise, dtype, mode, opts, min(shots, 64), seed)  # warm-up
+            st = _probe(circuit, noise, dtype, mode, opts, shots, seed)
+            ms = st["exec_ms"] / shots
+            rec = {"options": opts, "tile_qubits": st["tile_qubits"],
+                   "tile_buffers": st["tile_buffers"], "workers": st["workers"],
+                   "mfma": st["mfma"], "ms_per_shot": ms}
+            probes.append(rec)
+            if verbose:
+                print(f"[autotune] {rec}", flush=True)
+            if ms < best["ms_per_shot"]:
+                best = rec
     out = {"options": best["options"], "ms_per_shot": best["ms_per_shot"],
            "tile_qubits": best["tile_qubits"], "tile_buffers": best["tile_buffers"],
-           "workers": best["workers"], "probes": probes}
+           "workers": best["workers"], "mfma": best["mfma"], "probes": probes}
     if cache_path:
         cache[key] = out
         os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
