@@ -100,6 +100,21 @@ def test_plan_reorders_to_fewer_passes_than_list_order():
     assert opass.max() + 1 < 3 * layers  # list-order planning needs about 3 per layer
 
 
+def test_tile_set_search_is_deterministic_and_packs_passes():
+    # streamed states: each pass's tile set is the best of the greedy set,
+    # seeded candidates and single-qubit exchanges. The plan must not depend
+    # on anything but the circuit, and the search must reach the pass counts
+    # it was measured at (the greedy planner alone made 135 static passes on
+    # the 20-qubit circuit and 116 on the 26-qubit one, terminal pass included)
+    for name, k, most in (("c3_20q", 13, 131), ("c4_26q", 13, 89)):
+        w = W.workload(name)
+        a = _plan(w["circuit"], w["noise"], k, k - 8)
+        b = _plan(w["circuit"], w["noise"], k, k - 8)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+        assert len(a[3]) <= most, (name, len(a[3]))
+
+
 def test_rule_attaches_only_to_gates_of_its_width():
     # a one-qubit channel on the "unitary" kind: expanded after the 1-qubit
     # unitaries only, as the oracle expands it (the plan holds every
