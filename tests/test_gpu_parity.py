@@ -517,3 +517,37 @@ def test_parameter_sweep_with_conditional_ops(n, tile):
         ids = list(range(s * per, (s + 1) * per))
         exp = oracle.run(_with_angles(circ, params[s]), noise, ids, seed=4)
         assert mismatches(np.asarray(mem)[ids], exp) == 0
+
+
+def _ladder(n, reps, seed, u3=True):
+    rng = np.random.default_rng(seed)
+    ops = []
+    for _ in range(reps):
+        if u3:
+            for q in range(n):
+                ops.append({"kind": "u3", "qubits": [q],
+                            "params": [float(x) for x in rng.uniform(0, 2 * math.pi, 3)]})
+        for q in range(n - 1):
+            ops.append({"kind": "cx", "qubits": [q, q + 1]})
+    ops.append({"kind": "measure", "qubits": list(range(n)), "clbits": list(range(n))})
+    return {"n_qubits": n, "n_clbits": n, "ops": ops}
+
+
+@pytest.mark.parametrize("n,tile,u3,mode", [(12, 0, False, "batch"), (12, 0, False, "branch"),
+                                            (12, 0, True, "batch"), (12, 0, True, "branch"),
+                                            (10, 0, False, "batch"), (14, 12, True, "batch")])
+def test_passes_cut_at_group_and_matrix_room(n, tile, u3, mode):
+    # A 12-qubit complex128 state on the register-group engine plans passes
+    # of up to 512 ops. A CX ladder then gives 92 register groups in one
+    # pass (a pass holds 64), and U3 layers 135 fused one-qubit matrices
+    # (a pass holds 96): the fusion cuts the pass there and the next pass
+    # continues. Registers must equal the oracle's
+    circ = _ladder(n, 30, seed=n + tile, u3=u3)
+    noise = W.depol_model(p1=0.02, p2=0.05)
+    shots = 48
+    opts = {"tile_qubits": tile} if tile else {}
+    if n == 12:
+        opts["engine"] = 2
+    say(f"case pass cuts n={n} tile={tile} u3={u3} mode={mode}")
+    got = gpu_run(circ, noise, shots, dtype="c128", mode=mode, seed=8, **opts)
+    assert mismatches(got["memory"], oracle_memory(circ, noise, shots, seed=8)) == 0
