@@ -551,3 +551,21 @@ def test_passes_cut_at_group_and_matrix_room(n, tile, u3, mode):
     say(f"case pass cuts n={n} tile={tile} u3={u3} mode={mode}")
     got = gpu_run(circ, noise, shots, dtype="c128", mode=mode, seed=8, **opts)
     assert mismatches(got["memory"], oracle_memory(circ, noise, shots, seed=8)) == 0
+
+
+@pytest.mark.parametrize("n,mode", [(12, "batch"), (12, "branch"), (14, "batch")])
+def test_pass_cut_inside_one_register_group(n, mode):
+    # 300 CX gates on one pair form a single register group per pass; with
+    # strong two-qubit Pauli noise each CX flushes drawn factors, so a shot's
+    # pass needs more micro-ops than a pass holds (384) and is cut inside
+    # its first group
+    ops = [{"kind": "u3", "qubits": [q], "params": [0.3 * (q + 1), 0.2, 0.1]} for q in range(n)]
+    ops += [{"kind": "cx", "qubits": [0, 1]}] * 300
+    ops.append({"kind": "measure", "qubits": list(range(n)), "clbits": list(range(n))})
+    circ = {"n_qubits": n, "n_clbits": n, "ops": ops}
+    noise = W.depol_model(p1=0.05, p2=0.3)
+    shots = 32
+    opts = {"engine": 2} if n == 12 else {"tile_qubits": 13}
+    say(f"case cut inside one group n={n} mode={mode}")
+    got = gpu_run(circ, noise, shots, dtype="c128", mode=mode, seed=9, **opts)
+    assert mismatches(got["memory"], oracle_memory(circ, noise, shots, seed=9)) == 0
