@@ -211,10 +211,9 @@ sv_status sv_batch_create(int n_qubits, int64_t n_shots, sv_dtype dtype,
  *   "spin_elapsed" 1: the bound above counts from the start of each wait,
  *                  whatever the other workgroups do (forces the failure
  *                  path from the host in tests); 0 (default): watchdog
- *   "mfma"         complex64 fused one-qubit micro-ops: 0 automatic (on the
- *                  matrix cores when the circuit's register groups average
- *                  four or more one-qubit gates), 1 vector ALU, 2 matrix
- *                  cores. Results differ only by rounding
+ *   "mfma"         complex64 fused one-qubit micro-ops: 0 automatic (the
+ *                  matrix cores), 1 vector ALU, 2 matrix cores. Results
+ *                  differ only by rounding
  *   "graph"        1: a run's two launches (initialisation, then the
  *                  persistent executor) are kept as a HIP graph on the handle;
  *                  later runs update the launch arguments (seed, shot offset,

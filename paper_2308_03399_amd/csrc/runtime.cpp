@@ -1520,28 +1520,11 @@ static sv_status run_impl(sv_batch *b, const sv_op *ops, size_t n_ops, const sv_
     P.set_stride = set_stride;
     P.shots_per_set = sweep ? (uint32_t)((uint64_t)b->shots / n_sets) : 1u;
     {
-        // complex64 one-qubit micro-ops on the matrix cores: on request, or
-        // automatically when the register groups fuse many one-qubit gates
-        // (measured faster at 5.5 per group on the 26-qubit U3+CZ circuit,
-        // slower at 2.6 on the 20-qubit one, where the moves into the
-        // four-register result tuples cost more than the arithmetic saves)
-        int mf = 0;
-        if (b->dtype == SV_C64 && b->use_groups && b->opt_mfma != 1) {
-            if (b->opt_mfma == 2) {
-                mf = 1;
-            } else {
-                size_t g1 = 0, ng = 0;
-                for (const GroupInfo &gi : plan.groups)
-                    if (!gi.fallback) ++ng;
-                for (size_t pos = 0; pos < plan.order.size(); ++pos) {
-                    const XOp &x = xo[plan.order[pos]];
-                    if (x.kind > 0 && is_gate_kind((uint32_t)x.kind) && x.q.size() == 1 &&
-                        !plan.groups[plan.op_group[pos]].fallback)
-                        ++g1;
-                }
-                mf = (ng > 0 && g1 >= 4 * ng) ? 1 : 0;
-            }
-        }
+        // complex64 one-qubit micro-ops on the matrix cores unless the vector
+        // ALU is asked for: measured faster on the 20-qubit workload (2.6
+        // one-qubit gates per register group; 732 against 772 ms per 1024
+        // shots) and on the 26-qubit one (5.6 per group)
+        const int mf = (b->dtype == SV_C64 && b->use_groups && b->opt_mfma != 1) ? 1 : 0;
         P.mfma1 = mf;
         b->mfma = mf;
     }

@@ -4,8 +4,8 @@ four accumulating v_mfma_f32_4x4x1f32 per pair. The kept state must equal
 the FP64 oracle's amplitudes to complex64 rounding, and the per-shot
 registers the oracle's (up to a near-tie), on streamed tiles with one or
 two register sets and on LDS-resident states, in batch and branch mode.
-The automatic choice takes the matrix cores for circuits whose register
-groups average four or more one-qubit gates, and the vector ALU otherwise."""
+The automatic choice takes the matrix cores for complex64; option mfma=1
+keeps the vector ALU."""
 import numpy as np
 import pytest
 
@@ -44,10 +44,10 @@ def test_matrix_core_registers_match_oracle(mode):
     assert mismatches(got["memory"], exp) <= 1
 
 
-def test_automatic_choice_follows_one_qubit_gates_per_group():
-    # 26-qubit-style U3 + CZ layers fuse about 5.5 one-qubit gates per
-    # register group; the 20-qubit-style U3 + CX layers with amplitude
-    # damping about 2.6
+def test_automatic_choice_is_the_matrix_cores_for_complex64():
+    # measured faster on both the 20-qubit workload (2.6 one-qubit gates per
+    # register group) and the 26-qubit one (5.6): complex64 takes the
+    # matrix cores unless option mfma=1 asks for the vector ALU
     dense = W.random_layered(16, 12, seed=0, two_qubit="cz")
     say("case mfma automatic, U3+CZ layers")
     got = gpu_run(dense, W.depol_model(gates2=("cz",)), 8, dtype="c64", seed=0, tile_qubits=13)
@@ -55,6 +55,8 @@ def test_automatic_choice_follows_one_qubit_gates_per_group():
     sparse = W.workload("c3_20q")
     say("case mfma automatic, 20-qubit workload circuit")
     got = gpu_run(sparse["circuit"], sparse["noise"], 4, dtype="c64", seed=0)
+    assert got["stats"]["mfma"] == 1
+    got = gpu_run(sparse["circuit"], sparse["noise"], 4, dtype="c64", seed=0, mfma=1)
     assert got["stats"]["mfma"] == 0
     got = gpu_run(dense, W.depol_model(gates2=("cz",)), 8, dtype="c128", seed=0, tile_qubits=12)
     assert got["stats"]["mfma"] == 0  # complex128 always on the vector ALU
