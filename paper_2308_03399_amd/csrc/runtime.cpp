@@ -631,9 +631,14 @@ static size_t unit_end(const std::vector<XOp> &xo, const std::vector<uint32_t> &
 }
 
 // Tile sets tried per pass of a streamed state, besides the greedy one, and
-// rounds of single-qubit exchanges from the best of them
+// rounds of single-qubit exchanges from the best of them. The search is
+// bounded for large circuits: each candidate looks at most kSearchUnits
+// units ahead, and circuits of more than kSearchMaxOps expanded ops keep
+// the greedy sets (host planning stays well under a second)
 constexpr int kPassCandidates = 200;
 constexpr int kPassExchangeRounds = 4;
+constexpr size_t kSearchUnits = 4096;
+constexpr size_t kSearchMaxOps = 32768;
 
 static void plan_program(int n, int k, int r, bool resident, bool use_groups, uint32_t swz, int span,
                          const std::vector<XOp> &xo, const std::vector<Rule> &rules,
@@ -819,7 +824,7 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
     // the qubits in order of first use among the next units, and seeded
     // perturbations of that order, and keep the set that takes the most
     // ops (fewer passes over the state). Deterministic for a circuit.
-    const bool search = !resident && n > k;
+    const bool search = !resident && n > k && xo.size() <= kSearchMaxOps;
     uint64_t rng = 0x9e3779b97f4a7c15ull;
     auto next_rand = [&rng]() {
         // splitmix64
@@ -834,7 +839,7 @@ static void plan_program(int n, int k, int r, bool resident, bool use_groups, ui
         uint32_t blocked = 0;
         bool ord_blocked = false;
         size_t taken = 0;
-        for (size_t u = 0; u < um.size(); ++u) {
+        for (size_t u = 0; u < um.size() && u < kSearchUnits; ++u) {
             if (taken + ulen[u] > (size_t)kMaxPassOps) break;
             if (!(um[u] & blocked) && !(uord[u] && ord_blocked) && !(um[u] & ~C)) {
                 taken += ulen[u];
